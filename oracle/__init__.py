@@ -59,7 +59,7 @@ def lib():
         L.orc_background.restype = ctypes.c_double
         L.orc_background.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         L.orc_run.restype = ctypes.c_int
-        L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p] + [ctypes.c_void_p] * 8
+        L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p] + [ctypes.c_void_p] * 9
         L.orc_threads.restype = ctypes.c_int
         _LIB = L
         del dp
@@ -192,17 +192,18 @@ def run(cfg: Cfg, frames: np.ndarray, want_r: bool = False, want_rs: bool = Fals
     rs_last = np.zeros((H, W, cfg.nv), np.float64)
     r_all = np.zeros((T, H, W, cfg.nv), np.float64) if want_r else None
     rs_all = np.zeros((T, H, W, cfg.nv), np.float64) if want_rs else None
+    en_all = np.zeros((T, H, W), np.float64) if want_rs else None
     spec = np.zeros((H, W, cfg.Mx, cfg.My, cfg.Mz), np.complex128) if want_spec else None
     nbad = ctypes.c_longlong(0)
     c = cfg.c()
     rc = lib().orc_run(ctypes.byref(c), T, frames.ctypes.data, out.ctypes.data, vxy.ctypes.data,
-                       idx.ctypes.data, rs_last.ctypes.data, _p(r_all), _p(rs_all), _p(spec),
+                       idx.ctypes.data, rs_last.ctypes.data, _p(r_all), _p(rs_all), _p(en_all), _p(spec),
                        ctypes.addressof(nbad))
     if rc != 0:
         raise ValueError("orc_run failed with code %d" % rc)
     del HW
     return {"out": out, "vxy": vxy, "idx": idx, "rs_last": rs_last, "r_all": r_all,
-            "rs_all": rs_all, "spec": spec, "n_nonfinite": nbad.value}
+            "rs_all": rs_all, "en_all": en_all, "spec": spec, "n_nonfinite": nbad.value}
 
 
 def pixel_series(cfg: Cfg, frames: np.ndarray, x: int, y: int, T: int | None = None) -> dict:
@@ -215,12 +216,16 @@ def pixel_series(cfg: Cfg, frames: np.ndarray, x: int, y: int, T: int | None = N
         T = frames.shape[0]
     clean = np.where(np.isfinite(frames[:T]), frames[:T], 0.0).astype(np.float64)
     S = np.stack([brute.spectrum(clean, x, y, t, (cfg.Mx, cfg.My, cfg.Mz)) for t in range(T)])
-    R = flow_R(cfg, S)
+    R, P = flow_R(cfg, S, want_P=True)
     rs = np.zeros_like(R)
+    en = np.zeros(T)
     acc = np.zeros(cfg.nv)
+    eacc = 0.0
     for t in range(T):
         acc = (1.0 - cfg.alpha) * R[t] + cfg.alpha * acc
+        eacc = (1.0 - cfg.alpha) * P[t].sum() + cfg.alpha * eacc
         rs[t] = acc
+        en[t] = eacc
     idx = np.argmax(rs, axis=1).astype(np.int32)        # first maximum
     nvx = len(cfg.gx)
     cache = {}
@@ -240,7 +245,7 @@ def pixel_series(cfg: Cfg, frames: np.ndarray, x: int, y: int, T: int | None = N
         ts, xs, ys = t - cfg.dt, x - cfg.dx, y - cfg.dy
         ides = clean[ts, ys, xs] if (ts >= 0 and xs >= 0 and ys >= 0) else 0.0
         out[t] = ides - ihat[t]
-    return {"S": S, "R": R, "rs": rs, "idx": idx, "vxy": vxy, "ihat": ihat, "out": out}
+    return {"S": S, "R": R, "rs": rs, "en": en, "idx": idx, "vxy": vxy, "ihat": ihat, "out": out}
 
 
 def threads() -> int:

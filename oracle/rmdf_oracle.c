@@ -167,8 +167,8 @@ static void hann_axis(const int dims[3], int axis, const double complex *X, doub
       }
 }
 
-static void flow_R_tab(const orc_cfg *c, const double *rtab, const double complex *S,
-                       double *R, double *Pout, double complex *w1, double complex *w2) {
+static double flow_R_tab(const orc_cfg *c, const double *rtab, const double complex *S,
+                         double *R, double *Pout, double complex *w1, double complex *w2) {
   const int Mx = c->Mx, My = c->My, Mz = c->Mz, N = Mx * My * Mz;
   const int dims[3] = {Mx, My, Mz};
   /* high-pass: spatial components with kx = ky = 0 omitted (Sec. 2) */
@@ -182,7 +182,11 @@ static void flow_R_tab(const orc_cfg *c, const double *rtab, const double comple
   double *P = Pout;
   double *Ploc = NULL;
   if (!P) P = Ploc = malloc(sizeof(double) * N);
-  for (int i = 0; i < N; ++i) P[i] = creal(w2[i]) * creal(w2[i]) + cimag(w2[i]) * cimag(w2[i]);
+  double energy = 0.0;
+  for (int i = 0; i < N; ++i) {
+    P[i] = creal(w2[i]) * creal(w2[i]) + cimag(w2[i]) * cimag(w2[i]);
+    energy += P[i];
+  }
   /* eq. (10) on the candidate grid, l_z = 1 (real for even P) */
   const int nv = c->nvx * c->nvy;
   for (int i = 0; i < nv; ++i) {
@@ -192,6 +196,8 @@ static void flow_R_tab(const orc_cfg *c, const double *rtab, const double comple
     R[i] = s;
   }
   free(Ploc);
+  /* sum of P = R at zero lag, an upper bound of |R(l)| for every l */
+  return energy;
 }
 
 void orc_flow_R(const orc_cfg *c, int n, const double complex *S, double *R, double *P) {
@@ -236,7 +242,7 @@ static int cfg_ok(const orc_cfg *c) {
 
 int orc_run(const orc_cfg *c, int T, const float *frames,
             double *out, double *vxy, int *idx,
-            double *rs_last, double *r_all, double *rs_all,
+            double *rs_last, double *r_all, double *rs_all, double *en_all,
             double complex *spec_last, long long *n_nonfinite) {
   if (!cfg_ok(c) || T < 0 || !frames) return -1;
   const int H = c->H, W = c->W, Mx = c->Mx, My = c->My, Mz = c->Mz;
@@ -248,10 +254,11 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
   double complex *S2 = malloc(sizeof(double complex) * HW * Mx * My);
   double complex *a = calloc(HW * (size_t)N, sizeof(double complex));
   double *rs = calloc(HW * (size_t)nv, sizeof(double));
+  double *en = calloc(HW, sizeof(double));
   double *rtab = build_rtab(c);
   double complex *Hk = malloc(sizeof(double complex) * (size_t)(nv + 1) * N);
-  if (!img || !Sx || !S2 || !a || !rs || !rtab || !Hk) {
-    free(img); free(Sx); free(S2); free(a); free(rs); free(rtab); free(Hk);
+  if (!img || !Sx || !S2 || !a || !rs || !en || !rtab || !Hk) {
+    free(img); free(Sx); free(S2); free(a); free(rs); free(en); free(rtab); free(Hk);
     return -2;
   }
 
@@ -329,7 +336,9 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
           if (spec_last && t == T - 1) memcpy(spec_last + p * N, S, sizeof(double complex) * N);
 
           /* flow: eq. (9)-(10), then the first-order smoother */
-          flow_R_tab(c, rtab, S, R, NULL, w1, w2);
+          const double e0 = flow_R_tab(c, rtab, S, R, NULL, w1, w2);
+          en[p] = (1.0 - c->alpha) * e0 + c->alpha * en[p];
+          if (en_all) en_all[(size_t)t * HW + p] = en[p];
           double *rsp = rs + p * nv;
           for (int i = 0; i < nv; ++i) rsp[i] = (1.0 - c->alpha) * R[i] + c->alpha * rsp[i];
           if (r_all) memcpy(r_all + ((size_t)t * HW + p) * nv, R, sizeof(double) * nv);
@@ -355,6 +364,6 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
     }
   }
   if (rs_last) memcpy(rs_last, rs, sizeof(double) * HW * nv);
-  free(img); free(Sx); free(S2); free(a); free(rs); free(rtab); free(Hk);
+  free(img); free(Sx); free(S2); free(a); free(rs); free(en); free(rtab); free(Hk);
   return 0;
 }

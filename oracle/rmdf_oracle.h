@@ -75,13 +75,14 @@ double orc_background(const orc_cfg *c, const double complex *Hk,
  *   rs_last  H*W*nv   smoothed R after the last frame
  *   r_all    T*H*W*nv instantaneous R of every frame
  *   rs_all   T*H*W*nv smoothed R of every frame
+ *   en_all   T*H*W    smoothed sum of P (R at zero lag; bounds every |R|)
  *   spec_last H*W*Mx*My*Mz complex spectrum S(k; n) after the last frame
  * Non-finite input samples are replaced by 0 (their count is returned in
  * *n_nonfinite if that pointer is non-NULL).
  * Returns 0 on success, -1 on invalid configuration, -2 on allocation failure. */
 int orc_run(const orc_cfg *c, int T, const float *frames,
             double *out, double *vxy, int *idx,
-            double *rs_last, double *r_all, double *rs_all,
+            double *rs_last, double *r_all, double *rs_all, double *en_all,
             double complex *spec_last, long long *n_nonfinite);
 
 /* Number of OpenMP threads the pipeline uses (0 if built without OpenMP). */

@@ -1,0 +1,301 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars (FP32 GPU path vs FP64 oracle):
+  * velocity index: identical on >= 99.9% of non-tied anchors; an anchor is
+    tied when the oracle's top-two smoothed autocorrelation values differ by
+    <= 1e-4 of max(largest |R'|, 1e-3 E'), E' = the smoothed sum of the
+    power spectrum (R at zero lag, which bounds every |R|: the floor only
+    matters where R vanishes identically, e.g. before two frames have entered
+    the Hann-windowed temporal window); there the GPU's pick must be within
+    twice that gap of the oracle maximum;
+  * prediction-error output: |gpu - oracle| <= 1e-3 x RMS of the input frame
+    wherever the indices agree;
+  * local spectrum: max |gpu - oracle| <= 1e-4 x max |S| per anchor;
+  * smoothed autocorrelation: max |gpu - oracle| <= 1e-4 x max |R'| per anchor.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from paper_1408_3526_amd import scenes  # noqa: E402
+
+
+def _binding():
+    from paper_1408_3526_amd import binding
+    binding.lib()
+    return binding
+
+
+def _cfg(orc, H, W, M, gx, gy, **kw):
+    return orc.Cfg(H=H, W=W, Mx=M[0], My=M[1], Mz=M[2], gx=gx, gy=gy, **kw)
+
+
+def run_gpu(frames, M, gx, gy, spec_at=None, **kw):
+    b = _binding()
+    T, H, W = frames.shape
+    f = b.Filter(H, W, *M, gx, gy, **kw)
+    dev = torch.from_numpy(np.ascontiguousarray(frames)).cuda()
+    out, idx, vxy = [], [], []
+    for t in range(T):
+        f.push_frame(dev[t])
+        out.append(f.output().cpu().numpy())
+        v, i = f.velocity()
+        vxy.append(v.cpu().numpy())
+        idx.append(i.cpu().numpy())
+    res = {"out": np.stack(out), "idx": np.stack(idx), "vxy": np.stack(vxy),
+           "rs": f.smoothed_r().cpu().numpy(), "nonfinite": f.nonfinite_count()}
+    if spec_at is not None:
+        xs, ys = spec_at
+        res["spec"] = f.spectrum(xs, ys).cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+    return res
+
+
+def check_velocity_and_output(g, r, frames, nvx, gx, gy, min_agree=0.999, t0=0):
+    T = frames.shape[0]
+    stats = []
+    for t in range(t0, T):
+        rs = r["rs_all"][t]
+        srt = np.sort(rs, axis=-1)
+        scale = np.maximum(np.maximum(np.abs(rs).max(axis=-1), 1e-3 * r["en_all"][t]), 1e-30)
+        tied = (srt[..., -1] - srt[..., -2]) <= 1e-4 * scale
+        gi, oi = g["idx"][t], r["idx"][t]
+        agree = gi == oi
+        nt = ~tied
+        frac = agree[nt].mean() if nt.any() else 1.0
+        assert frac >= min_agree, (t, frac)
+        # where they differ, the GPU pick is (near-)maximal for the oracle
+        dis = ~agree
+        if dis.any():
+            picked = np.take_along_axis(rs, np.clip(gi, 0, rs.shape[-1] - 1)[..., None], -1)[..., 0]
+            gap = srt[..., -1] - picked
+            assert np.all(gap[dis] <= 2e-4 * scale[dis] + 1e-12), (t, gap[dis].max())
+        rms = float(np.sqrt(np.mean(frames[t].astype(np.float64) ** 2)))
+        err = np.abs(g["out"][t] - r["out"][t])[agree]
+        if err.size:
+            assert err.max() <= 1e-3 * rms, (t, err.max(), rms)
+        # velocity values are the grid values of the index
+        ok = gi >= 0
+        assert np.array_equal(g["vxy"][t][..., 0][ok], gx[gi[ok] % nvx].astype(np.float32))
+        assert np.array_equal(g["vxy"][t][..., 1][ok], gy[gi[ok] // nvx].astype(np.float32))
+        stats.append((frac, err.max() / rms if err.size else 0.0))
+    return stats
+
+
+def check_rs(g, r):
+    ref = r["rs_all"][-1]
+    scale = np.maximum(np.abs(ref).max(axis=-1, keepdims=True), 1e-30)
+    rel = (np.abs(g["rs"].astype(np.float64) - ref) / scale).max()
+    assert rel <= 1e-4, rel
+    return rel
+
+
+def check_spec(g, r, xs, ys):
+    for i, (x, y) in enumerate(zip(xs, ys)):
+        ref = r["spec"][y, x]
+        err = np.abs(g["spec"][i] - ref).max()
+        assert err <= 1e-4 * np.abs(ref).max(), (x, y, err, np.abs(ref).max())
+
+
+def test_parity_64x64_window_8x8x4(orc):
+    """64x64, 32 frames, 8x8x4, 9x9 integer grid: clutter translating at (1,-2)."""
+    sc = scenes.translate_scene(0, H=64, W=64, T=32, v=(1, -2), n_targets=3)
+    g = scenes.grid(-4, 4, 1.0)
+    M = (8, 8, 4)
+    xs, ys = np.array([0, 63, 7, 31, 50]), np.array([0, 63, 40, 31, 3])
+    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys))
+    r = orc.run(_cfg(orc, 64, 64, M, g, g), sc.frames, want_rs=True, want_spec=True)
+    check_spec(gres, r, xs, ys)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
+    # the clutter velocity is found where the window is full
+    assert np.mean(gres["idx"][-1, 7:, 7:] == r["idx"][-1, 7:, 7:]) >= 0.999
+
+
+@pytest.mark.parametrize("H,W,tile", [(45, 37, 16), (33, 70, 8), (5, 6, 32), (1, 13, 4)])
+def test_parity_ragged_8x8x4(orc, H, W, tile):
+    """Frame sizes that leave ragged tails in both tile dimensions, frames
+    smaller than the window, and a single-row frame."""
+    rng = np.random.default_rng(H * 100 + W)
+    T = 9
+    fr = (scenes.gaussian_field(rng, 2 * H + 8, 2 * W + 8, 10.0)[:H, :W] + 100.0)
+    fr = np.stack([np.roll(fr, (t, -t), (0, 1)) + rng.normal(size=(H, W)) for t in range(T)]).astype(np.float32)
+    g = scenes.grid(-2, 2, 1.0)
+    M = (8, 8, 4)
+    gres = run_gpu(fr, M, g, g, tile_rows=tile)
+    r = orc.run(_cfg(orc, H, W, M, g, g), fr, want_rs=True)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, fr, len(g), g, g)
+
+
+def test_parity_window_16x16x8_flow(orc):
+    """16x16x8 window, 17x17 grid at 0.5 px/frame, non-uniform flow with an
+    occluding band and targets; several row tiles with a ragged tail."""
+    sc = scenes.flow_scene(5, H=40, W=47, T=12, n_targets=3, band_width=(8, 12))
+    g = scenes.grid(-4, 4, 0.5)
+    M = (16, 16, 8)
+    xs, ys = np.array([0, 46, 20, 15, 46]), np.array([0, 39, 20, 33, 0])
+    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), tile_rows=16)
+    r = orc.run(_cfg(orc, 40, 47, M, g, g), sc.frames, want_rs=True, want_spec=True)
+    check_spec(gres, r, xs, ys)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
+
+
+def test_parity_paper_configuration(orc):
+    """The paper's parameters: 9x9x5 window (K = 4, 4, 2), B = 3, m' = K,
+    17x17 grid at 0.25 px/frame, on the paper's simulated scene."""
+    sc = scenes.paper_scene(7, T=16)
+    g = scenes.grid(-2, 2, 0.25)
+    M = (9, 9, 5)
+    xs, ys = np.array([0, 63, 30, 8]), np.array([0, 63, 33, 50])
+    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), Bx=3, By=3)
+    r = orc.run(_cfg(orc, 64, 64, M, g, g, Bx=3, By=3), sc.frames, want_rs=True, want_spec=True)
+    check_spec(gres, r, xs, ys)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
+
+
+@pytest.mark.parametrize("M,B,v", [((8, 8, 4), 3, (0.7, -1.3)), ((16, 16, 8), 6, (-2.3, 0.45)),
+                                   ((9, 9, 5), 3, (1.625, 0.625))])
+def test_fixed_velocity_pef_null(orc, M, B, v):
+    """Band-limited clutter translating at v is removed (fixed-velocity mode)."""
+    rng = np.random.default_rng(6)
+    H, W, T = M[1] + 9, M[0] + 11, M[2] + 4
+    ys, xs = np.mgrid[0:H, 0:W].astype(float)
+    fr = np.full((T, H, W), 10.0)
+    comps = [(rng.integers(-B, B + 1), rng.integers(-B, B + 1), rng.uniform(0.5, 2.0),
+              rng.uniform(0, 2 * np.pi)) for _ in range(12)]
+    for t in range(T):
+        for kx, ky, a, ph in comps:
+            fr[t] += a * np.cos(2 * np.pi * (kx * (xs - v[0] * t) / M[0] + ky * (ys - v[1] * t) / M[1]) + ph)
+    fr = fr.astype(np.float32)
+    b = _binding()
+    gres = run_gpu(fr, M, np.zeros(1), np.zeros(1), Bx=B, By=B, velocity_mode=b.VEL_FIXED, fixed_v=v)
+    r = orc.run(_cfg(orc, H, W, M, np.zeros(1), np.zeros(1), Bx=B, By=B, vmode=2, fvx=v[0], fvy=v[1]), fr)
+    rms = float(np.sqrt(np.mean(fr.astype(np.float64) ** 2)))
+    assert np.abs(gres["out"] - r["out"]).max() <= 1e-3 * rms
+    assert np.all(gres["idx"] == -1)
+    valid = gres["out"][M[2] - 1:, M[1] - 1:, M[0] - 1:]
+    assert np.abs(valid).max() <= 1e-3 * rms
+
+
+def test_full_band_moving_average_on_gpu(orc):
+    """Odd window with B = K and v = 0: output = delayed pixel minus the
+    temporal moving average (parity with the oracle, which is pinned to the
+    closed form)."""
+    rng = np.random.default_rng(8)
+    T, H, W = 9, 20, 21
+    fr = (rng.normal(size=(T, H, W)) * 4 + 30).astype(np.float32)
+    b = _binding()
+    M = (9, 9, 5)
+    gres = run_gpu(fr, M, np.zeros(1), np.zeros(1), Bx=4, By=4, velocity_mode=b.VEL_FIXED, fixed_v=(0.0, 0.0))
+    f = fr.astype(np.float64)
+    for t in range(M[2] - 1, T):
+        want = f[t - 2, 4:H - 4, 4:W - 4] - f[t - 4:t + 1, 4:H - 4, 4:W - 4].mean(0)
+        got = gres["out"][t, 8:, 8:]
+        assert np.abs(got - want).max() <= 1e-3 * 30
+
+
+def test_nonfinite_input_on_gpu(orc):
+    rng = np.random.default_rng(10)
+    T, H, W = 6, 24, 30
+    fr = (rng.normal(size=(T, H, W)) + 50).astype(np.float32)
+    bad = fr.copy()
+    bad[1, 3, 4] = np.nan
+    bad[3, 10, 20] = np.inf
+    bad[4, 0, 0] = -np.inf
+    zero = np.where(np.isfinite(bad), bad, 0).astype(np.float32)
+    g = scenes.grid(-2, 2, 1.0)
+    a = run_gpu(bad, (8, 8, 4), g, g)
+    z = run_gpu(zero, (8, 8, 4), g, g)
+    assert a["nonfinite"] == 3 and z["nonfinite"] == 0
+    assert np.array_equal(a["out"], z["out"]) and np.array_equal(a["idx"], z["idx"])
+    assert np.all(np.isfinite(a["out"]))
+
+
+def test_deterministic():
+    sc = scenes.translate_scene(4, H=40, W=44, T=8, v=(-1, 1))
+    g = scenes.grid(-3, 3, 1.0)
+    a = run_gpu(sc.frames, (8, 8, 4), g, g)
+    b = run_gpu(sc.frames, (8, 8, 4), g, g)
+    for k in ("out", "idx", "vxy", "rs"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_state_errors():
+    b = _binding()
+    g = scenes.grid(-1, 1, 1.0)
+    f = b.Filter(16, 16, 8, 8, 4, g, g)
+    with pytest.raises(b.RmdfError) as e:
+        f.output()
+    assert e.value.status == b.RMDF_E_STATE
+    f.push_frame(torch.zeros(16, 16, device="cuda"))
+    with pytest.raises(b.RmdfError) as e:
+        f.spectrum([16], [0])
+    assert e.value.status == b.RMDF_E_INVAL
+    with pytest.raises(ValueError):
+        f.push_frame(torch.zeros(15, 16, device="cuda"))
+    f.close()
+
+
+def _sampled_full_size(orc, sc, M, g, pts, T, **kw):
+    """Full-size run on the GPU; the oracle computes the sampled anchors one by
+    one from the direct window spectrum."""
+    gres = run_gpu(sc.frames[:T], M, g, g, spec_at=(pts[:, 0], pts[:, 1]), **kw)
+    cfg = _cfg(orc, sc.frames.shape[1], sc.frames.shape[2], M, g, g)
+    nvx = len(g)
+    agree_n = tot_n = 0
+    for i, (x, y) in enumerate(pts):
+        p = orc.pixel_series(cfg, sc.frames, int(x), int(y), T=T)
+        # spectrum of the last frame
+        ref = p["S"][-1]
+        assert np.abs(gres["spec"][i] - ref).max() <= 1e-4 * np.abs(ref).max()
+        for t in range(T):
+            rs = p["rs"][t]
+            srt = np.sort(rs)
+            scale = max(np.abs(rs).max(), 1e-3 * p["en"][t], 1e-30)
+            tied = srt[-1] - srt[-2] <= 1e-4 * scale
+            gi = gres["idx"][t, y, x]
+            if gi == p["idx"][t]:
+                rms = float(np.sqrt(np.mean(sc.frames[t].astype(np.float64) ** 2)))
+                assert abs(gres["out"][t, y, x] - p["out"][t]) <= 1e-3 * rms
+                agree_n += 1
+            else:
+                assert tied, (x, y, t)
+                assert srt[-1] - rs[gi] <= 2e-4 * scale
+            tot_n += 0 if tied else 1
+        sm = gres["rs"][y, x].astype(np.float64)
+        assert np.abs(sm - p["rs"][-1]).max() <= 1e-4 * np.abs(p["rs"][-1]).max()
+    assert agree_n >= 0.999 * tot_n
+    del nvx
+
+
+def _sample_points(rng, H, W, n):
+    pts = [(0, 0), (W - 1, H - 1), (W - 1, 0), (0, H - 1), (W // 2, H // 2)]
+    pts += [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(n)]
+    return np.array(pts)
+
+
+def test_sampled_parity_640x512_window_16x16x8(orc):
+    """The benchmark workload's shape and launch configuration (640x512,
+    16x16x8, 17x17 grid at 0.5), sampled anchors."""
+    T = 12
+    sc = scenes.flow_scene(1, H=512, W=640, T=T, n_targets=20)
+    g = scenes.grid(-4, 4, 0.5)
+    pts = _sample_points(np.random.default_rng(0), 512, 640, 20)
+    _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T)
+
+
+def test_sampled_parity_1280x1024_window_16x16x8(orc):
+    """Largest single-GPU frame (1280x1024, 10.7 GB observer state)."""
+    T = 9
+    sc = scenes.flow_scene(2, H=1024, W=1280, T=T, n_targets=50, varying_noise=True)
+    g = scenes.grid(-4, 4, 0.5)
+    pts = _sample_points(np.random.default_rng(1), 1024, 1280, 10)
+    _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T)
