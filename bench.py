@@ -1,0 +1,161 @@
+"""Benchmark: pixel-frames/s of the whole per-frame path on one MI355X.
+
+Workload: 640x512 FP32 frames, 16x16x8 analysis window, 17x17 candidate
+velocities on a 0.5 px/frame grid over [-4, 4]; smooth non-uniform clutter
+flow with an occluding band, 20 point targets and sigma = 1 noise (seeded
+synthetic frames, generated before timing and resident in HBM).
+
+One step = one frame pushed through the whole path (ingest, row sliding DFT,
+per-pixel kernel).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
+
+WORKLOADS = {
+    "640x512": dict(H=512, W=640, M=(16, 16, 8), grid=(-4.0, 4.0, 0.5), frames=200, seed=1, targets=20),
+    "1280x1024": dict(H=1024, W=1280, M=(16, 16, 8), grid=(-4.0, 4.0, 0.5), frames=100, seed=2, targets=50),
+    "64x64": dict(H=64, W=64, M=(8, 8, 4), grid=(-4.0, 4.0, 1.0), frames=32, seed=0, targets=3),
+}
+
+
+def algorithmic_bytes_per_pixel_frame(M, nv):
+    """Bytes the method itself must move per pixel and frame: observer state
+    read + write (Mx*My*Mz reals of a Hermitian spectrum, FP32), smoothed
+    autocorrelation read + write (nv FP32), frame in, delayed frame in,
+    output out, velocity (2 FP32) out."""
+    Mx, My, Mz = M
+    return 2 * 4 * Mx * My * Mz + 2 * 4 * nv + 4 + 4 + 4 + 8
+
+
+def make_frames(wl):
+    from paper_1408_3526_amd import scenes
+    H, W = wl["H"], wl["W"]
+    if wl["M"] == (8, 8, 4):
+        return scenes.translate_scene(wl["seed"], H=H, W=W, T=wl["frames"], v=(1, -2), n_targets=wl["targets"]).frames
+    return scenes.flow_scene(wl["seed"], H=H, W=W, T=wl["frames"], n_targets=wl["targets"],
+                             varying_noise=(H >= 1024)).frames
+
+
+def cpu_baseline(frames, wl, g, budget_frames=8, crop=64):
+    """The FP64 oracle, as it is, on a bounded sample: a crop x crop window of
+    the same frames for budget_frames frames, on all host cores."""
+    import numpy as np
+
+    import oracle
+    sub = np.ascontiguousarray(frames[:budget_frames, :crop, :crop])
+    cfg = oracle.Cfg(H=sub.shape[1], W=sub.shape[2], Mx=wl["M"][0], My=wl["M"][1], Mz=wl["M"][2], gx=g, gy=g)
+    oracle.lib()
+    t0 = time.perf_counter()
+    oracle.run(cfg, sub)
+    dt = time.perf_counter() - t0
+    n = sub.shape[0] * sub.shape[1] * sub.shape[2]
+    return {"value": n / dt, "unit": "pixel-frames/s", "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%dx%d crop of the workload's frames, %d frames (%d pixel-frames, %.1f s)"
+                      % (sub.shape[1], sub.shape[2], sub.shape[0], n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=24)
+    ap.add_argument("--workload", default="640x512", choices=sorted(WORKLOADS))
+    ap.add_argument("--frames", type=int, default=0, help="distinct synthetic frames (0: workload default)")
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the per-pixel state shards by row strips; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1408_3526_amd import binding, scenes
+
+    wl = dict(WORKLOADS[args.workload])
+    if args.frames:
+        wl["frames"] = args.frames
+    H, W, M = wl["H"], wl["W"], wl["M"]
+    g = scenes.grid(*wl["grid"])
+    nv = len(g) ** 2
+    t0 = time.perf_counter()
+    frames = make_frames(wl)
+    print("generated %d frames in %.1f s" % (frames.shape[0], time.perf_counter() - t0), file=sys.stderr, flush=True)
+
+    torch.cuda.set_device(0)
+    dev = torch.from_numpy(frames).cuda()
+    T = dev.shape[0]
+    f = binding.Filter(H, W, *M, g, g, tile_rows=args.tile_rows)
+    stream = torch.cuda.current_stream()
+
+    for i in range(args.warmup):
+        f.push_frame(dev[i % T])
+    torch.cuda.synchronize()
+    f.set_timing(True)
+    f.kernel_time(0)   # reset counters
+    f.kernel_time(1)
+    f.kernel_time(2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        f.push_frame(dev[(args.warmup + i) % T])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    ms = e0.elapsed_time(e1)
+    kms = {k: f.kernel_time(k) for k in (0, 1, 2)}
+    f.set_timing(False)
+    out = f.output()
+    assert torch.isfinite(out).all()
+    f.close()
+
+    px_frames = args.steps * H * W
+    value = px_frames / (ms / 1e3)
+    bpp = algorithmic_bytes_per_pixel_frame(M, nv)
+    pix_ms = kms[0][0] / max(kms[0][1], 1)
+    achieved = bpp * H * W / (pix_ms / 1e3) / 1e9
+    res = {
+        "metric": "pixel-frames/s @640x512, 16x16x8 window; % HBM peak; learned vs plain velocity",
+        "value": value,
+        "unit": "pixel-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%dx%d frames, %dx%dx%d window, %dx%d velocity grid (%.2g px/frame), "
+                               "plain autocorrelation search" % (W, H, M[0], M[1], M[2], len(g), len(g), g[1] - g[0]),
+                   "frames_distinct": int(T), "tile_rows": args.tile_rows or 32},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_pixel<%d,%d,%d>" % M, "kernel_ms": pix_ms,
+                     "algorithmic_bytes_per_pixel_frame": bpp},
+        "kernel_ms": {"pixel": pix_ms, "row": kms[1][0] / max(kms[1][1], 1), "ingest": kms[2][0] / max(kms[2][1], 1)},
+        "wall_s": wall,
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(frames, wl, g)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

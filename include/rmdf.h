@@ -1,0 +1,144 @@
+/*
+ * rmdf.h - C ABI of the MI355X recursive multidimensional prediction-error
+ * filter (Kennedy, arXiv:1408.3526: "Parallel software implementation of
+ * recursive multidimensional digital filters for point-target detection in
+ * cluttered infrared scenes").
+ *
+ * The library turns a stream of monochrome frames I(x, y, t) into
+ *   - the prediction-error (whitened) output: the frame delayed by m' minus
+ *     the velocity-tuned background estimate (Sec. 2, eq. 1 and 4);
+ *   - the per-pixel background velocity from the local 3-D autocorrelation
+ *     (Sec. 2, eq. 9-10, argmax on the l_z = 1 slice);
+ * using a local 3-D spectrum per pixel that is updated recursively every
+ * frame (Sec. 1: sliding DFTs along rows and columns, a deadbeat observer in
+ * time; eq. 6-7).
+ *
+ * Conventions
+ *   - Every call returns rmdf_status; no C++ exception crosses the ABI.
+ *   - Frames and outputs are DEVICE pointers (HIP), FP32, row-major [y][x],
+ *     owned by the caller; they must stay valid until the context's stream
+ *     has executed the call.  Host-side arrays (candidate grids, weights) are
+ *     copied before the call returns.
+ *   - All device work is enqueued on the context's HIP stream; calls return
+ *     without waiting.  Synchronise that stream before reading results.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Window lengths Kx, Ky, Kt are the analysis-window lengths M (the DFT
+ *     sizes), not the paper's half-widths K (the paper uses M = 2K + 1).
+ *   - Outputs are indexed by the window anchor: out[y][x] after the push of
+ *     frame t is the whitened value of pixel (x - m'_x, y - m'_y) of frame
+ *     t - m'_t, computed from the window whose newest corner is (x, y, t).
+ *     Samples outside the frame or before the first frame count as zero.
+ *   - Non-finite input samples are replaced by 0 and counted.
+ */
+#ifndef RMDF_H
+#define RMDF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmdf_ctx rmdf_ctx;
+
+typedef enum {
+  RMDF_OK = 0,
+  RMDF_E_INVAL = -1,        /* invalid argument (message in rmdf_last_error) */
+  RMDF_E_NOMEM = -2,        /* device allocation failed                      */
+  RMDF_E_DEVICE = -3,       /* no HIP device, or a HIP call/launch failed     */
+  RMDF_E_STATE = -4,        /* call out of order (e.g. output before a push)  */
+  RMDF_E_UNSUPPORTED = -5   /* window shape without a compiled kernel         */
+} rmdf_status;
+
+typedef enum {
+  RMDF_VEL_SEARCH = 0,      /* argmax of the smoothed autocorrelation (Sec. 2) */
+  RMDF_VEL_LEARNED = 1,     /* learned surrogate, search where confidence low  */
+  RMDF_VEL_FIXED = 2        /* one velocity for every pixel (fixed_vx, fixed_vy) */
+} rmdf_velocity_mode;
+
+typedef struct {
+  int Bx, By;               /* filter half-bandwidth B (eq. 2; W = 2B+1 bins).
+                               -1: floor(3M/8) (M = 9 gives the paper's B = 3).
+                               Valid: 0 <= B <= floor((M-1)/2).               */
+  int delay_x, delay_y, delay_t; /* output delay m' (Sec. 3). -1: floor(M/2)
+                               (M = 9, 5 give the paper's m' = K).  0 <= m' < M */
+  float alpha;              /* pole of the first-order smoother of R (Sec. 2).
+                               < 0: exp(-1/10) (Sec. 3).  Valid: [0, 1).       */
+  int velocity_mode;        /* rmdf_velocity_mode                              */
+  float fixed_vx, fixed_vy; /* velocity used by RMDF_VEL_FIXED                  */
+  float conf_threshold;     /* RMDF_VEL_LEARNED: search below this confidence  */
+  int tile_rows;            /* rows per work tile of the pixel kernel; 0: auto  */
+} rmdf_params;
+
+/* Fill *p with the defaults above (the -1 / negative markers). */
+void rmdf_params_default(rmdf_params *p);
+
+/* Create a filter for H x W frames with window lengths Kx x Ky x Kt and the
+ * candidate velocity grid vgrid_x[nvx] x vgrid_y[nvy] (host arrays, pixels per
+ * frame; candidate index i = iy * nvx + ix).  p == NULL: defaults.
+ * hip_stream: the hipStream_t every call of this context enqueues on; NULL
+ * means the device's default (null) stream.
+ * Allocates all device state (observer state H*W*Kx*Ky*Kt/2 complex FP32,
+ * smoothed autocorrelation H*W*nvx*nvy FP32, row spectra, a (m'_t+1)-frame
+ * delay ring, tables) and zeroes it.
+ * Compiled window shapes: 8x8x4, 16x16x8, 9x9x5 (others: RMDF_E_UNSUPPORTED).
+ * Errors: RMDF_E_INVAL (H, W < 1 or H > 65535; bad B, m', alpha; nvx, nvy outside [1, 33],
+ * non-finite grid; out == NULL), RMDF_E_DEVICE, RMDF_E_NOMEM. */
+rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt,
+                        const float *vgrid_x, int nvx, const float *vgrid_y, int nvy,
+                        const rmdf_params *p, void *hip_stream, rmdf_ctx **out);
+
+/* Push the next frame (device pointer, H*W FP32) and run the whole per-frame
+ * path on the context stream: frame ingest into the delay ring, row sliding
+ * DFT, then the per-pixel kernel (column sliding DFT, observer update,
+ * high-pass + Hann + power spectrum, autocorrelation on the grid, smoothing,
+ * argmax, velocity-tuned background estimate, output).
+ * Errors: RMDF_E_INVAL (NULL), RMDF_E_DEVICE (launch failure). */
+rmdf_status rmdf_push_frame(rmdf_ctx *ctx, const float *frame_dev);
+
+/* Copy the velocity field of the latest frame into caller buffers:
+ * vxy_dev[H*W*2] = (vx, vy) per anchor; idx_dev[H*W] = candidate index
+ * (-1 where a fixed velocity was used); either may be NULL.
+ * Errors: RMDF_E_STATE before the first push. */
+rmdf_status rmdf_velocity(rmdf_ctx *ctx, float *vxy_dev, int *idx_dev);
+
+/* Copy the prediction-error output of the latest frame into out_dev[H*W].
+ * Errors: RMDF_E_STATE before the first push. */
+rmdf_status rmdf_output(rmdf_ctx *ctx, float *out_dev);
+
+/* Frames pushed so far, and non-finite input samples replaced by zero (the
+ * count is read back from the device and synchronises the stream). */
+rmdf_status rmdf_frames_pushed(const rmdf_ctx *ctx, long long *n);
+rmdf_status rmdf_nonfinite_count(rmdf_ctx *ctx, long long *n);
+
+/* Local 3-D spectrum S(k; n) (eq. 6, newest sample at m = 0) of the latest
+ * frame at anchors (xs[i], ys[i]), i < npix (host arrays), written to the
+ * device buffer spec_dev[npix][Kx][Ky][Kt] as interleaved complex FP32.
+ * Intended for verification.  Errors: RMDF_E_INVAL, RMDF_E_STATE. */
+rmdf_status rmdf_spectrum(rmdf_ctx *ctx, int npix, const int *xs, const int *ys, float *spec_dev);
+
+/* Smoothed autocorrelation R' of the latest frame on the candidate grid,
+ * rs_dev[H*W][nvx*nvy] (device, FP32). Errors: RMDF_E_STATE. */
+rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);
+
+/* Per-kernel timing with HIP events on the context stream (off by default).
+ * which: 0 = pixel kernel, 1 = row sliding-DFT kernel, 2 = ingest.
+ * Returns the summed milliseconds and the number of timed launches since the
+ * last reset (reading synchronises the stream). */
+rmdf_status rmdf_set_timing(rmdf_ctx *ctx, int on);
+rmdf_status rmdf_kernel_time(rmdf_ctx *ctx, int which, double *ms, long long *launches);
+
+/* Bytes of device memory the context holds. */
+rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);
+
+/* Free everything; ctx may be NULL. */
+rmdf_status rmdf_destroy(rmdf_ctx *ctx);
+
+/* Message of the last error on ctx (NULL ctx: the calling thread's last
+ * rmdf_create error).  Never NULL. */
+const char *rmdf_last_error(const rmdf_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMDF_H */

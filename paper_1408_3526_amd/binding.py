@@ -1,0 +1,243 @@
+"""ctypes binding of librmdf.so (C ABI in include/rmdf.h).
+
+Argument marshalling only: every step of the filter runs in the HIP library.
+Device buffers are torch tensors on a HIP device (their ``data_ptr()`` is
+passed through); torch supplies memory and streams and nothing else.  There is
+no CPU fallback: if librmdf.so is missing, ``lib()`` raises.
+
+The module-level functions carry the C names; ``Filter`` wraps a context.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "librmdf.so")
+_LIB = None
+
+RMDF_OK, RMDF_E_INVAL, RMDF_E_NOMEM, RMDF_E_DEVICE, RMDF_E_STATE, RMDF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+VEL_SEARCH, VEL_LEARNED, VEL_FIXED = 0, 1, 2
+
+_STATUS = {0: "RMDF_OK", -1: "RMDF_E_INVAL", -2: "RMDF_E_NOMEM", -3: "RMDF_E_DEVICE",
+           -4: "RMDF_E_STATE", -5: "RMDF_E_UNSUPPORTED"}
+
+
+class RmdfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, str(status)), msg))
+        self.status = status
+
+
+class rmdf_params(ctypes.Structure):
+    _fields_ = [("Bx", ctypes.c_int), ("By", ctypes.c_int),
+                ("delay_x", ctypes.c_int), ("delay_y", ctypes.c_int), ("delay_t", ctypes.c_int),
+                ("alpha", ctypes.c_float), ("velocity_mode", ctypes.c_int),
+                ("fixed_vx", ctypes.c_float), ("fixed_vy", ctypes.c_float),
+                ("conf_threshold", ctypes.c_float), ("tile_rows", ctypes.c_int)]
+
+
+# C signatures: name -> (restype, argtypes)
+_VP, _I, _LL, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double, ctypes.c_size_t
+_SIGS = {
+    "rmdf_params_default": (None, [ctypes.POINTER(rmdf_params)]),
+    "rmdf_create": (_I, [_I, _I, _I, _I, _I, _VP, _I, _VP, _I, ctypes.POINTER(rmdf_params), _VP,
+                         ctypes.POINTER(_VP)]),
+    "rmdf_push_frame": (_I, [_VP, _VP]),
+    "rmdf_velocity": (_I, [_VP, _VP, _VP]),
+    "rmdf_output": (_I, [_VP, _VP]),
+    "rmdf_frames_pushed": (_I, [_VP, ctypes.POINTER(_LL)]),
+    "rmdf_nonfinite_count": (_I, [_VP, ctypes.POINTER(_LL)]),
+    "rmdf_spectrum": (_I, [_VP, _I, _VP, _VP, _VP]),
+    "rmdf_smoothed_r": (_I, [_VP, _VP]),
+    "rmdf_set_timing": (_I, [_VP, _I]),
+    "rmdf_kernel_time": (_I, [_VP, _I, ctypes.POINTER(_D), ctypes.POINTER(_LL)]),
+    "rmdf_device_bytes": (_I, [_VP, ctypes.POINTER(_SZ)]),
+    "rmdf_destroy": (_I, [_VP]),
+    "rmdf_last_error": (ctypes.c_char_p, [_VP]),
+}
+
+
+def lib():
+    """Load librmdf.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(SO_PATH):
+            raise RuntimeError("librmdf.so is not built (run __graft_entry__.build() or "
+                               "python paper_1408_3526_amd/build.py); there is no fallback")
+        L = ctypes.CDLL(SO_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def exported_names():
+    return list(_SIGS)
+
+
+def _check(status: int, ctx=None):
+    if status != RMDF_OK:
+        msg = lib().rmdf_last_error(ctx)
+        raise RmdfError(status, msg.decode() if msg else "")
+
+
+def _dev_ptr(t, dtype=None, numel=None, name="tensor"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a HIP device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must have dtype %s" % (name, dtype))
+    if numel is not None and t.numel() != numel:
+        raise ValueError("%s must have %d elements, has %d" % (name, numel, t.numel()))
+    return t.data_ptr()
+
+
+# ---- C-named functions -------------------------------------------------------
+
+def rmdf_params_default() -> rmdf_params:
+    p = rmdf_params()
+    lib().rmdf_params_default(ctypes.byref(p))
+    return p
+
+
+def rmdf_create(H, W, Kx, Ky, Kt, vgrid_x, vgrid_y, params: rmdf_params | None = None, stream=None):
+    gx = np.ascontiguousarray(vgrid_x, np.float32)
+    gy = np.ascontiguousarray(vgrid_y, np.float32)
+    ctx = _VP()
+    s = None if stream is None else ctypes.c_void_p(int(stream))
+    st = lib().rmdf_create(int(H), int(W), int(Kx), int(Ky), int(Kt), gx.ctypes.data, len(gx),
+                           gy.ctypes.data, len(gy), None if params is None else ctypes.byref(params), s,
+                           ctypes.byref(ctx))
+    _check(st, None)
+    return ctx
+
+
+def rmdf_push_frame(ctx, frame_ptr: int):
+    _check(lib().rmdf_push_frame(ctx, frame_ptr), ctx)
+
+
+def rmdf_velocity(ctx, vxy_ptr, idx_ptr):
+    _check(lib().rmdf_velocity(ctx, vxy_ptr, idx_ptr), ctx)
+
+
+def rmdf_output(ctx, out_ptr):
+    _check(lib().rmdf_output(ctx, out_ptr), ctx)
+
+
+def rmdf_destroy(ctx):
+    lib().rmdf_destroy(ctx)
+
+
+# ---- convenience wrapper -----------------------------------------------------
+
+class Filter:
+    """One filter context.  Every call is enqueued on the torch stream that was
+    current when the Filter was created (or on ``stream``, a raw hipStream_t
+    handle); tensors passed in and returned belong to that stream."""
+
+    def __init__(self, H, W, Kx, Ky, Kt, vgrid_x, vgrid_y, *, Bx=-1, By=-1, delay=(-1, -1, -1),
+                 alpha=-1.0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0), conf_threshold=0.9,
+                 tile_rows=0, stream=None, use_torch_stream=True):
+        import torch
+        p = rmdf_params_default()
+        p.Bx, p.By = int(Bx), int(By)
+        p.delay_x, p.delay_y, p.delay_t = (int(v) for v in delay)
+        p.alpha = float(alpha)
+        p.velocity_mode = int(velocity_mode)
+        p.fixed_vx, p.fixed_vy = (float(v) for v in fixed_v)
+        p.conf_threshold = float(conf_threshold)
+        p.tile_rows = int(tile_rows)
+        if stream is None and use_torch_stream:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.H, self.W, self.M = int(H), int(W), (int(Kx), int(Ky), int(Kt))
+        self.nvx, self.nvy = len(vgrid_x), len(vgrid_y)
+        self.nv = self.nvx * self.nvy
+        self.gx = np.asarray(vgrid_x, np.float32)
+        self.gy = np.asarray(vgrid_y, np.float32)
+        self.ctx = rmdf_create(H, W, Kx, Ky, Kt, vgrid_x, vgrid_y, p, stream)
+
+    def push_frame(self, frame):
+        import torch
+        rmdf_push_frame(self.ctx, _dev_ptr(frame, torch.float32, self.H * self.W, "frame"))
+
+    def output(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.H, self.W), dtype=torch.float32, device="cuda")
+        rmdf_output(self.ctx, _dev_ptr(out, torch.float32, self.H * self.W, "out"))
+        return out
+
+    def velocity(self, vxy=None, idx=None):
+        import torch
+        if vxy is None:
+            vxy = torch.empty((self.H, self.W, 2), dtype=torch.float32, device="cuda")
+        if idx is None:
+            idx = torch.empty((self.H, self.W), dtype=torch.int32, device="cuda")
+        rmdf_velocity(self.ctx, _dev_ptr(vxy, torch.float32, 2 * self.H * self.W, "vxy"),
+                      _dev_ptr(idx, torch.int32, self.H * self.W, "idx"))
+        return vxy, idx
+
+    def spectrum(self, xs, ys):
+        import torch
+        xs = np.ascontiguousarray(xs, np.int32)
+        ys = np.ascontiguousarray(ys, np.int32)
+        n = len(xs)
+        Mx, My, Mz = self.M
+        out = torch.empty((n, Mx, My, Mz, 2), dtype=torch.float32, device="cuda")
+        _check(lib().rmdf_spectrum(self.ctx, n, xs.ctypes.data, ys.ctypes.data, out.data_ptr()), self.ctx)
+        return torch.view_as_complex(out)
+
+    def smoothed_r(self):
+        import torch
+        out = torch.empty((self.H, self.W, self.nv), dtype=torch.float32, device="cuda")
+        _check(lib().rmdf_smoothed_r(self.ctx, out.data_ptr()), self.ctx)
+        return out
+
+    def set_timing(self, on: bool):
+        _check(lib().rmdf_set_timing(self.ctx, int(bool(on))), self.ctx)
+
+    def kernel_time(self, which: int):
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        _check(lib().rmdf_kernel_time(self.ctx, int(which), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
+        return ms.value, n.value
+
+    def frames_pushed(self) -> int:
+        n = ctypes.c_longlong()
+        _check(lib().rmdf_frames_pushed(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def nonfinite_count(self) -> int:
+        n = ctypes.c_longlong()
+        _check(lib().rmdf_nonfinite_count(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def device_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().rmdf_device_bytes(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            rmdf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

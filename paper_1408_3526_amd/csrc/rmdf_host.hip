@@ -1,0 +1,450 @@
+// rmdf_host.hip - host side of the C ABI declared in include/rmdf.h:
+// context lifetime, argument checking, coefficient/twiddle tables (built in
+// double precision, rounded to FP32), launch order, optional kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/rmdf.h"
+#include "rmdf_kernels.h"
+
+using cd = std::complex<double>;
+static const double kPi = 3.14159265358979323846264338327950288;
+
+namespace {
+thread_local std::string g_create_error;
+
+struct EventPair {
+  hipEvent_t a, b;
+  int which;
+};
+}  // namespace
+
+struct rmdf_ctx {
+  int H = 0, W = 0, MX = 0, MY = 0, MZ = 0, NP = 0, NCOL = 0;
+  int nvx = 0, nvy = 0, nv = 0;
+  int Bx = 0, By = 0, dx = 0, dy = 0, dt = 0, vmode = 0, TY = 32;
+  float alpha = 0.f, fvx = 0.f, fvy = 0.f, conf = 0.9f;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  long long t = 0;
+  int nring = 1;
+  // device buffers
+  float* ring = nullptr;
+  float2* rs = nullptr;
+  float2* st = nullptr;
+  float* rsm = nullptr;
+  float* out = nullptr;
+  float2* vxy = nullptr;
+  int* vidx = nullptr;
+  float2 *twx = nullptr, *twy = nullptr, *twz = nullptr, *twA = nullptr;
+  float2 *tauy = nullptr, *taux = nullptr, *htab = nullptr;
+  float *gx = nullptr, *gy = nullptr;
+  unsigned long long* nonfinite = nullptr;
+  int* xy_scratch = nullptr;
+  int xy_cap = 0;
+  size_t bytes = 0;
+  std::vector<void*> allocs;
+  // timing
+  bool timing = false;
+  std::vector<EventPair> events;
+  double ms[3] = {0, 0, 0};
+  long long launches[3] = {0, 0, 0};
+  std::string err;
+};
+
+static rmdf_status fail(rmdf_ctx* c, rmdf_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+static rmdf_status hip_fail(rmdf_ctx* c, hipError_t e, const char* what) {
+  return fail(c, RMDF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+static hipError_t dalloc(rmdf_ctx* c, T** p, size_t n) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, n * sizeof(T) > 0 ? n * sizeof(T) : 1);
+  if (e != hipSuccess) return e;
+  c->allocs.push_back(q);
+  c->bytes += n * sizeof(T);
+  *p = static_cast<T*>(q);
+  return hipSuccess;
+}
+
+static void free_all(rmdf_ctx* c) {
+  for (void* p : c->allocs) hipFree(p);
+  c->allocs.clear();
+  for (auto& ev : c->events) { hipEventDestroy(ev.a); hipEventDestroy(ev.b); }
+  c->events.clear();
+  if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
+  c->stream = nullptr;
+}
+
+// Trigonometric weight of DFT bin k at (possibly non-integer) lag l on M
+// points: exp(+j 2 pi kc l / M) for the centred representative kc, and
+// cos(pi l) for the even-M Nyquist bin (its two representatives +-M/2 each
+// carry half the weight).
+static cd trig_weight(int M, int k, double l) {
+  if (2 * k == M) return cd(std::cos(kPi * l), 0.0);
+  const int kc = (2 * k < M) ? k : k - M;
+  const double ph = 2.0 * kPi * kc * l / M;
+  return cd(std::cos(ph), std::sin(ph));
+}
+
+static double dirichlet(int n, double w) {
+  const double r = std::nearbyint(w);
+  if (std::fabs(w - r) < 1e-12) {
+    const long long e = (long long)(n - 1) * (long long)r;
+    return (e % 2 == 0) ? 1.0 : -1.0;
+  }
+  return std::sin(kPi * n * w) / (n * std::sin(kPi * w));
+}
+
+// Background coefficient at bin (kx, ky, kz) for velocity v: the velocity-
+// tuned response evaluated at the DFT bins (Sec. 2, eq. 8 with f = k/M).  At
+// the bins the spatial Dirichlet factors select the single band term kx'=kx,
+// ky'=ky (centred), leaving
+//   (MxMyMz)^-1/2 exp(-j2pi(kx m'x/Mx + ky m'y/My)) exp(+j2pi phi (m'z - Dz))
+//   exp(-j2pi kz Dz/Mz) D_Mz(kz/Mz + phi),   phi = vx kx/Mx + vy ky/My,
+// Dz = (Mz-1)/2.  kx, ky are centred band indices.
+static cd coeff(const rmdf_ctx* c, int kx, int ky, int kz, double vx, double vy) {
+  const double N = (double)c->MX * c->MY * c->MZ;
+  const double phi = vx * kx / c->MX + vy * ky / c->MY;
+  const double Dz = 0.5 * (c->MZ - 1);
+  const double ph = -2.0 * kPi * ((double)kx * c->dx / c->MX + (double)ky * c->dy / c->MY) +
+                    2.0 * kPi * phi * (c->dt - Dz) - 2.0 * kPi * kz * Dz / c->MZ;
+  return (dirichlet(c->MZ, (double)kz / c->MZ + phi) / std::sqrt(N)) * cd(std::cos(ph), std::sin(ph));
+}
+
+template <class T>
+static hipError_t upload(rmdf_ctx* c, T** dst, const std::vector<T>& v) {
+  hipError_t e = dalloc(c, dst, v.size());
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+static float2 f2(cd z) { return make_float2((float)z.real(), (float)z.imag()); }
+
+static hipError_t build_tables(rmdf_ctx* c, const float* gxh, const float* gyh) {
+  hipError_t e;
+  std::vector<float2> twx(c->MX), twy(c->MY), twz(c->MZ), twA(c->MZ);
+  for (int k = 0; k < c->MX; ++k) twx[k] = f2(std::polar(1.0, 2 * kPi * k / c->MX));
+  for (int k = 0; k < c->MY; ++k) twy[k] = f2(std::polar(1.0, 2 * kPi * k / c->MY));
+  for (int k = 0; k < c->MZ; ++k) twz[k] = f2(std::polar(1.0, 2 * kPi * k / c->MZ));
+  // P = Mz/4096 |h'|^2 (S = sqrt(Mz) X; each axis' Hann is h'/4), l_z = 1
+  for (int k = 0; k < c->MZ; ++k) twA[k] = f2(std::polar((double)c->MZ / 4096.0, 2 * kPi * k / c->MZ));
+  if ((e = upload(c, &c->twx, twx)) != hipSuccess) return e;
+  if ((e = upload(c, &c->twy, twy)) != hipSuccess) return e;
+  if ((e = upload(c, &c->twz, twz)) != hipSuccess) return e;
+  if ((e = upload(c, &c->twA, twA)) != hipSuccess) return e;
+
+  const int NXH = c->MX / 2 + 1;
+  std::vector<float2> tauy((size_t)c->nvy * c->MY), taux((size_t)c->nvx * NXH);
+  for (int iy = 0; iy < c->nvy; ++iy)
+    for (int k = 0; k < c->MY; ++k) tauy[(size_t)iy * c->MY + k] = f2(trig_weight(c->MY, k, gyh[iy]));
+  for (int ix = 0; ix < c->nvx; ++ix)
+    for (int k = 0; k < NXH; ++k) {
+      // kx and -kx contribute complex-conjugate terms: weight 2 except for
+      // the self-conjugate kx = 0 and kx = Mx/2 (even Mx)
+      const double w = (k == 0 || 2 * k == c->MX) ? 1.0 : 2.0;
+      taux[(size_t)ix * NXH + k] = f2(w * trig_weight(c->MX, k, gxh[ix]));
+    }
+  if ((e = upload(c, &c->tauy, tauy)) != hipSuccess) return e;
+  if ((e = upload(c, &c->taux, taux)) != hipSuccess) return e;
+
+  // background coefficients per candidate (+ the fixed velocity), stored
+  // for kx in [0, Bx] (weight 1 for kx = 0, 2 for kx > 0: the -kx terms are
+  // conjugates), ky in [-By, By], all kz; sqrt(Mz) folded in (S = sqrt(Mz) X)
+  const int nbx = c->Bx + 1, nby = 2 * c->By + 1;
+  std::vector<float2> htab((size_t)(c->nv + 1) * nbx * nby * c->MZ);
+  const double sz = std::sqrt((double)c->MZ);
+  for (int i = 0; i <= c->nv; ++i) {
+    const double vx = (i < c->nv) ? gxh[i % c->nvx] : c->fvx;
+    const double vy = (i < c->nv) ? gyh[i / c->nvx] : c->fvy;
+    for (int kx = 0; kx < nbx; ++kx)
+      for (int j = 0; j < nby; ++j)
+        for (int kz = 0; kz < c->MZ; ++kz) {
+          const double w = (kx == 0) ? 1.0 : 2.0;
+          htab[(((size_t)i * nbx + kx) * nby + j) * c->MZ + kz] = f2(w * sz * coeff(c, kx, j - c->By, kz, vx, vy));
+        }
+  }
+  if ((e = upload(c, &c->htab, htab)) != hipSuccess) return e;
+  std::vector<float> gx(gxh, gxh + c->nvx), gy(gyh, gyh + c->nvy);
+  if ((e = upload(c, &c->gx, gx)) != hipSuccess) return e;
+  if ((e = upload(c, &c->gy, gy)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+extern "C" {
+
+void rmdf_params_default(rmdf_params* p) {
+  if (!p) return;
+  p->Bx = p->By = -1;
+  p->delay_x = p->delay_y = p->delay_t = -1;
+  p->alpha = -1.0f;
+  p->velocity_mode = RMDF_VEL_SEARCH;
+  p->fixed_vx = p->fixed_vy = 0.0f;
+  p->conf_threshold = 0.9f;
+  p->tile_rows = 0;
+}
+
+rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid_x, int nvx, const float* vgrid_y,
+                        int nvy, const rmdf_params* pin, void* hip_stream, rmdf_ctx** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, RMDF_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (H < 1 || W < 1) return fail(nullptr, RMDF_E_INVAL, "frame size must be at least 1x1");
+  if (H > 65535) return fail(nullptr, RMDF_E_INVAL, "frame height must be <= 65535");
+  if (Kx < 2 || Ky < 2 || Kt < 2) return fail(nullptr, RMDF_E_INVAL, "window lengths must be >= 2");
+  if (!vgrid_x || !vgrid_y) return fail(nullptr, RMDF_E_INVAL, "velocity grid pointer is NULL");
+  if (nvx < 1 || nvy < 1 || nvx > rmdf::NVX_MAX || nvy > rmdf::NVY_MAX)
+    return fail(nullptr, RMDF_E_INVAL, "velocity grid sizes must be in [1, 33]");
+  for (int i = 0; i < nvx; ++i)
+    if (!std::isfinite(vgrid_x[i])) return fail(nullptr, RMDF_E_INVAL, "non-finite velocity grid value");
+  for (int i = 0; i < nvy; ++i)
+    if (!std::isfinite(vgrid_y[i])) return fail(nullptr, RMDF_E_INVAL, "non-finite velocity grid value");
+  rmdf_params p;
+  if (pin) p = *pin;
+  else rmdf_params_default(&p);
+  const int Bx = p.Bx < 0 ? (3 * Kx) / 8 : p.Bx;
+  const int By = p.By < 0 ? (3 * Ky) / 8 : p.By;
+  if (Bx > (Kx - 1) / 2 || By > (Ky - 1) / 2) return fail(nullptr, RMDF_E_INVAL, "B must be <= floor((M-1)/2)");
+  const int dx = p.delay_x < 0 ? Kx / 2 : p.delay_x;
+  const int dy = p.delay_y < 0 ? Ky / 2 : p.delay_y;
+  const int dt = p.delay_t < 0 ? Kt / 2 : p.delay_t;
+  if (dx >= Kx || dy >= Ky || dt >= Kt) return fail(nullptr, RMDF_E_INVAL, "delay m' must be < M");
+  const float alpha = p.alpha < 0.f ? std::exp(-0.1f) : p.alpha;
+  if (!(alpha >= 0.f && alpha < 1.f)) return fail(nullptr, RMDF_E_INVAL, "alpha must be in [0, 1)");
+  if (p.velocity_mode != RMDF_VEL_SEARCH && p.velocity_mode != RMDF_VEL_FIXED)
+    return fail(nullptr, RMDF_E_UNSUPPORTED, "velocity mode not available in this context type");
+  if (p.velocity_mode == RMDF_VEL_FIXED && !(std::isfinite(p.fixed_vx) && std::isfinite(p.fixed_vy)))
+    return fail(nullptr, RMDF_E_INVAL, "fixed velocity must be finite");
+  if (p.tile_rows < 0) return fail(nullptr, RMDF_E_INVAL, "tile_rows must be >= 0");
+  if (!rmdf::shape_supported(Kx, Ky, Kt))
+    return fail(nullptr, RMDF_E_UNSUPPORTED, "window shape has no compiled kernel (8x8x4, 16x16x8, 9x9x5)");
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) return fail(nullptr, RMDF_E_DEVICE, "no HIP device available");
+
+  rmdf_ctx* c = new (std::nothrow) rmdf_ctx();
+  if (!c) return fail(nullptr, RMDF_E_NOMEM, "host allocation failed");
+  hipGetDevice(&c->device);
+  c->H = H; c->W = W; c->MX = Kx; c->MY = Ky; c->MZ = Kt;
+  c->NP = rmdf::planes_for(Kx);
+  c->NCOL = c->NP * Ky;
+  c->nvx = nvx; c->nvy = nvy; c->nv = nvx * nvy;
+  c->Bx = Bx; c->By = By; c->dx = dx; c->dy = dy; c->dt = dt;
+  c->alpha = alpha; c->vmode = p.velocity_mode; c->fvx = p.fixed_vx; c->fvy = p.fixed_vy;
+  c->conf = p.conf_threshold;
+  c->TY = p.tile_rows > 0 ? p.tile_rows : 32;
+  c->nring = dt + 1;
+  // NULL: the device's default (null) stream, which is also torch's default
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  c->own_stream = false;
+  const size_t HW = (size_t)H * W;
+  auto bail = [&](hipError_t err, const char* what) {
+    rmdf_status s = (err == hipErrorOutOfMemory || err == hipErrorMemoryAllocation)
+                        ? fail(nullptr, RMDF_E_NOMEM, std::string(what) + ": out of device memory")
+                        : hip_fail(nullptr, err, what);
+    free_all(c);
+    delete c;
+    return s;
+  };
+  if ((e = dalloc(c, &c->ring, HW * c->nring)) != hipSuccess) return bail(e, "ring");
+  if ((e = dalloc(c, &c->rs, HW * c->NP)) != hipSuccess) return bail(e, "row spectra");
+  if ((e = dalloc(c, &c->st, HW * c->NCOL * Kt)) != hipSuccess) return bail(e, "observer state");
+  if ((e = dalloc(c, &c->rsm, HW * c->nv)) != hipSuccess) return bail(e, "smoothed autocorrelation");
+  if ((e = dalloc(c, &c->out, HW)) != hipSuccess) return bail(e, "output");
+  if ((e = dalloc(c, &c->vxy, HW)) != hipSuccess) return bail(e, "velocity");
+  if ((e = dalloc(c, &c->vidx, HW)) != hipSuccess) return bail(e, "velocity index");
+  if ((e = dalloc(c, &c->nonfinite, 1)) != hipSuccess) return bail(e, "counter");
+  if ((e = build_tables(c, vgrid_x, vgrid_y)) != hipSuccess) return bail(e, "tables");
+  // zero the state (observer, smoother, ring) on the context stream
+  if ((e = hipMemsetAsync(c->st, 0, HW * c->NCOL * Kt * sizeof(float2), c->stream)) != hipSuccess) return bail(e, "memset");
+  if ((e = hipMemsetAsync(c->rsm, 0, HW * c->nv * sizeof(float), c->stream)) != hipSuccess) return bail(e, "memset");
+  if ((e = hipMemsetAsync(c->ring, 0, HW * c->nring * sizeof(float), c->stream)) != hipSuccess) return bail(e, "memset");
+  if ((e = hipMemsetAsync(c->nonfinite, 0, sizeof(unsigned long long), c->stream)) != hipSuccess) return bail(e, "memset");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "sync");
+  *out = c;
+  return RMDF_OK;
+}
+
+static void timed_begin(rmdf_ctx* c, int which, EventPair* ev) {
+  if (!c->timing) return;
+  hipEventCreate(&ev->a);
+  hipEventCreate(&ev->b);
+  ev->which = which;
+  hipEventRecord(ev->a, c->stream);
+}
+static void timed_end(rmdf_ctx* c, EventPair* ev) {
+  if (!c->timing) return;
+  hipEventRecord(ev->b, c->stream);
+  c->events.push_back(*ev);
+}
+
+rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (!frame) return fail(c, RMDF_E_INVAL, "frame is NULL");
+  const size_t HW = (size_t)c->H * c->W;
+  float* slot = c->ring + HW * (size_t)(c->t % c->nring);
+  EventPair ev{};
+  hipError_t e;
+  timed_begin(c, 2, &ev);
+  e = rmdf::launch_ingest(frame, slot, (long long)HW, c->nonfinite, c->stream);
+  timed_end(c, &ev);
+  if (e != hipSuccess) return hip_fail(c, e, "ingest launch");
+  timed_begin(c, 1, &ev);
+  e = rmdf::launch_row(c->MX, slot, c->rs, c->twx, c->H, c->W, c->stream);
+  timed_end(c, &ev);
+  if (e != hipSuccess) return hip_fail(c, e, "row kernel launch");
+
+  rmdf::PixArgs a{};
+  a.H = c->H; a.W = c->W; a.TY = c->TY;
+  a.nvx = c->nvx; a.nvy = c->nvy; a.nv = c->nv;
+  a.bx = c->Bx; a.by = c->By; a.dx = c->dx; a.dy = c->dy;
+  a.vmode = c->vmode;
+  a.alpha = c->alpha; a.inv_sqrt_my = (float)(1.0 / std::sqrt((double)c->MY));
+  a.fvx = c->fvx; a.fvy = c->fvy;
+  a.rs = c->rs; a.st = c->st; a.rsm = c->rsm;
+  a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
+  a.out = c->out; a.vxy = c->vxy; a.vidx = c->vidx;
+  a.twy = c->twy; a.twz = c->twz; a.twA = c->twA; a.tauy = c->tauy; a.taux = c->taux; a.htab = c->htab;
+  a.gx = c->gx; a.gy = c->gy;
+  timed_begin(c, 0, &ev);
+  e = rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
+  timed_end(c, &ev);
+  if (e != hipSuccess) return hip_fail(c, e, "pixel kernel launch");
+  c->t += 1;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_velocity(rmdf_ctx* c, float* vxy, int* idx) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
+  const size_t HW = (size_t)c->H * c->W;
+  hipError_t e;
+  if (vxy && (e = hipMemcpyAsync(vxy, c->vxy, HW * sizeof(float2), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "velocity copy");
+  if (idx && (e = hipMemcpyAsync(idx, c->vidx, HW * sizeof(int), hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "index copy");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_output(rmdf_ctx* c, float* out) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (!out) return fail(c, RMDF_E_INVAL, "out is NULL");
+  if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
+  hipError_t e = hipMemcpyAsync(out, c->out, (size_t)c->H * c->W * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "output copy");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_frames_pushed(const rmdf_ctx* c, long long* n) {
+  if (!c || !n) return RMDF_E_INVAL;
+  *n = c->t;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_nonfinite_count(rmdf_ctx* c, long long* n) {
+  if (!c || !n) return fail(c, RMDF_E_INVAL, "NULL argument");
+  unsigned long long v = 0;
+  hipError_t e = hipMemcpyAsync(&v, c->nonfinite, sizeof(v), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "counter read");
+  *n = (long long)v;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, float* spec) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (npix < 0 || (npix > 0 && (!xs || !ys || !spec))) return fail(c, RMDF_E_INVAL, "bad arguments");
+  if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
+  if (npix == 0) return RMDF_OK;
+  std::vector<int> xy(2 * (size_t)npix);
+  for (int i = 0; i < npix; ++i) {
+    if (xs[i] < 0 || xs[i] >= c->W || ys[i] < 0 || ys[i] >= c->H) return fail(c, RMDF_E_INVAL, "anchor outside the frame");
+    xy[2 * i] = xs[i];
+    xy[2 * i + 1] = ys[i];
+  }
+  hipError_t e;
+  if (npix > c->xy_cap) {
+    if ((e = dalloc(c, &c->xy_scratch, 2 * (size_t)npix)) != hipSuccess) return hip_fail(c, e, "scratch");
+    c->xy_cap = npix;
+  }
+  if ((e = hipMemcpyAsync(c->xy_scratch, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "anchor upload");
+  e = rmdf::launch_spectrum(c->MX, c->MY, c->MZ, c->st, c->W, c->xy_scratch, npix, reinterpret_cast<float2*>(spec),
+                            c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "spectrum launch");
+  // the host array must outlive the copy
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "sync");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_smoothed_r(rmdf_ctx* c, float* rs) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (!rs) return fail(c, RMDF_E_INVAL, "rs is NULL");
+  if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
+  hipError_t e = hipMemcpyAsync(rs, c->rsm, (size_t)c->H * c->W * c->nv * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_set_timing(rmdf_ctx* c, int on) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  c->timing = on != 0;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_kernel_time(rmdf_ctx* c, int which, double* ms, long long* launches) {
+  if (!c || which < 0 || which > 2 || !ms || !launches) return fail(c, RMDF_E_INVAL, "bad arguments");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "sync");
+  for (auto& ev : c->events) {
+    float t = 0.f;
+    hipEventElapsedTime(&t, ev.a, ev.b);
+    c->ms[ev.which] += t;
+    c->launches[ev.which] += 1;
+    hipEventDestroy(ev.a);
+    hipEventDestroy(ev.b);
+  }
+  c->events.clear();
+  *ms = c->ms[which];
+  *launches = c->launches[which];
+  c->ms[which] = 0;
+  c->launches[which] = 0;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_device_bytes(const rmdf_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return RMDF_E_INVAL;
+  *bytes = c->bytes;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_destroy(rmdf_ctx* c) {
+  if (!c) return RMDF_OK;
+  if (c->stream) hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+  return RMDF_OK;
+}
+
+const char* rmdf_last_error(const rmdf_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,46 @@
+// rmdf_kernels.h - launch interface between the host library and the gfx950
+// kernels of the recursive multidimensional prediction-error filter.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rmdf {
+
+constexpr int RCX = 256;       // columns per row-kernel block
+constexpr int RSEG = 16;       // columns per resonator segment (direct-DFT seed at its start)
+constexpr int NVY_MAX = 33;    // largest candidate grid per axis
+constexpr int NVX_MAX = 33;
+
+// Arguments of the per-pixel kernel (passed by value).
+struct PixArgs {
+  int H, W, TY;                // frame size, rows per work tile
+  int nvx, nvy, nv;            // candidate grid
+  int bx, by, dx, dy;          // half-bandwidth, spatial output delay
+  int vmode;                   // 0 search, 2 fixed velocity
+  float alpha, inv_sqrt_my;
+  float fvx, fvy;
+  const float2* rs;            // row spectra [planes][H][W]
+  float2* st;                  // observer state [H][W][planes*My][Mz]
+  float* rsm;                  // smoothed autocorrelation [H][W][nv]
+  const float* ring_delayed;   // input frame t - m'_t, or nullptr while t < m'_t
+  float* out;                  // [H][W]
+  float2* vxy;                 // [H][W]
+  int* vidx;                   // [H][W]
+  const float2* twy;           // [My]  w_y^k
+  const float2* twz;           // [Mz]  w_z^k
+  const float2* twA;           // [Mz]  stage-A weights (w_z^k and scale)
+  const float2* tauy;          // [nvy][My]  trigonometric weights along ky
+  const float2* taux;          // [nvx][Mx/2+1] weights along kx (Hermitian factor folded)
+  const float2* htab;          // [nv+1][bx+1][2by+1][Mz] background coefficients
+  const float* gx;             // [nvx]
+  const float* gy;             // [nvy]
+};
+
+bool shape_supported(int mx, int my, int mz);
+int planes_for(int mx);
+hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s);
+hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s);
+hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
+                           hipStream_t s);
+hipError_t launch_ingest(const float* in, float* slot, long long n, unsigned long long* nonfinite, hipStream_t s);
+
+}  // namespace rmdf

@@ -171,6 +171,9 @@ def flow_scene(seed: int, H: int = 512, W: int = 640, T: int = 200, n_targets: i
     tg = _targets(st["targets"], n_targets, H, W, T, max_target_speed)
     amps = st["targets"].uniform(snr[0], snr[1], n_targets) * noise_sigma
 
+    # cubic-spline coefficients of the periodic canvases, computed once
+    Gc = _ndi.spline_filter(G, order=3, mode="grid-wrap")
+    Gbc = _ndi.spline_filter(Gb, order=3, mode="grid-wrap")
     frames = np.zeros((T, H, W), np.float32)
     mask_all = np.zeros((T, H, W), bool)
     Dx = np.zeros((H, W))
@@ -184,14 +187,14 @@ def flow_scene(seed: int, H: int = 512, W: int = 640, T: int = 200, n_targets: i
             Dy_prev = _ndi.map_coordinates(Dy, [cy, cx], order=1, mode="nearest")
             Dx = -v[..., 0] + Dx_prev
             Dy = -v[..., 1] + Dy_prev
-        img = _ndi.map_coordinates(G, [ys + Dy, xs + Dx], order=3, mode="grid-wrap")
+        img = _ndi.map_coordinates(Gc, [ys + Dy, xs + Dx], order=3, mode="grid-wrap", prefilter=False)
         if band:
             c_t = bc + bv * t
             dist = (xs - c_t[0]) * nrm[0] + (ys - c_t[1]) * nrm[1]
             m = np.abs(dist) < 0.5 * bw
             if m.any():
-                bimg = _ndi.map_coordinates(Gb, [ys[m] - bv[1] * t, xs[m] - bv[0] * t],
-                                            order=3, mode="grid-wrap")
+                bimg = _ndi.map_coordinates(Gbc, [ys[m] - bv[1] * t, xs[m] - bv[0] * t],
+                                            order=3, mode="grid-wrap", prefilter=False)
                 img[m] = bimg
             mask_all[t] = m
         for i in range(n_targets):
