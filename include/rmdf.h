@@ -68,6 +68,9 @@ typedef struct {
   float fixed_vx, fixed_vy; /* velocity used by RMDF_VEL_FIXED                  */
   float conf_threshold;     /* RMDF_VEL_LEARNED: search below this confidence  */
   int tile_rows;            /* rows per work tile of the pixel kernel; 0: auto  */
+  int kernel_variant;       /* per-pixel kernel: 0 auto, 1 generic (LDS-staged,
+                               any compiled shape), 2 one wavefront per anchor
+                               (16x16x8, at most 21 candidates per axis)       */
 } rmdf_params;
 
 /* Fill *p with the defaults above (the -1 / negative markers). */

@@ -36,7 +36,8 @@ class rmdf_params(ctypes.Structure):
                 ("delay_x", ctypes.c_int), ("delay_y", ctypes.c_int), ("delay_t", ctypes.c_int),
                 ("alpha", ctypes.c_float), ("velocity_mode", ctypes.c_int),
                 ("fixed_vx", ctypes.c_float), ("fixed_vy", ctypes.c_float),
-                ("conf_threshold", ctypes.c_float), ("tile_rows", ctypes.c_int)]
+                ("conf_threshold", ctypes.c_float), ("tile_rows", ctypes.c_int),
+                ("kernel_variant", ctypes.c_int)]
 
 
 # C signatures: name -> (restype, argtypes)
@@ -146,7 +147,7 @@ class Filter:
 
     def __init__(self, H, W, Kx, Ky, Kt, vgrid_x, vgrid_y, *, Bx=-1, By=-1, delay=(-1, -1, -1),
                  alpha=-1.0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0), conf_threshold=0.9,
-                 tile_rows=0, stream=None, use_torch_stream=True):
+                 tile_rows=0, kernel_variant=0, stream=None, use_torch_stream=True):
         import torch
         p = rmdf_params_default()
         p.Bx, p.By = int(Bx), int(By)
@@ -156,6 +157,7 @@ class Filter:
         p.fixed_vx, p.fixed_vy = (float(v) for v in fixed_v)
         p.conf_threshold = float(conf_threshold)
         p.tile_rows = int(tile_rows)
+        p.kernel_variant = int(kernel_variant)
         if stream is None and use_torch_stream:
             stream = torch.cuda.current_stream().cuda_stream
         self.H, self.W, self.M = int(H), int(W), (int(Kx), int(Ky), int(Kt))

@@ -46,7 +46,8 @@ struct rmdf_ctx {
   int* vidx = nullptr;
   float2 *twx = nullptr, *twy = nullptr, *twz = nullptr, *twA = nullptr;
   float2 *tauy = nullptr, *taux = nullptr, *htab = nullptr;
-  float *gx = nullptr, *gy = nullptr;
+  float *gx = nullptr, *gy = nullptr, *tabB = nullptr, *tabC = nullptr;
+  int variant = 0;                 // resolved kernel variant (1 generic, 2 wave-per-anchor)
   unsigned long long* nonfinite = nullptr;
   int* xy_scratch = nullptr;
   int xy_cap = 0;
@@ -179,6 +180,28 @@ static hipError_t build_tables(rmdf_ctx* c, const float* gxh, const float* gyh) 
         }
   }
   if ((e = upload(c, &c->htab, htab)) != hipSuccess) return e;
+  // register-resident weights of the wave-per-anchor 16x16x8 kernel: along
+  // ky, cos and sin of 2 pi k l / 16 for k = 1..7 and cos(pi l) (Nyquist);
+  // along kx the same with the Hermitian factor 2 folded in
+  if (c->MX == 16 && c->MY == 16) {
+    std::vector<float> tb((size_t)c->nvy * 16, 0.f), tc((size_t)c->nvx * 16, 0.f);
+    for (int iy = 0; iy < c->nvy; ++iy) {
+      for (int k = 1; k < 8; ++k) {
+        tb[iy * 16 + k - 1] = (float)std::cos(2 * kPi * k * gyh[iy] / 16.0);
+        tb[iy * 16 + 6 + k] = (float)std::sin(2 * kPi * k * gyh[iy] / 16.0);
+      }
+      tb[iy * 16 + 14] = (float)std::cos(kPi * gyh[iy]);
+    }
+    for (int ix = 0; ix < c->nvx; ++ix) {
+      for (int k = 1; k < 8; ++k) {
+        tc[ix * 16 + k - 1] = (float)(2.0 * std::cos(2 * kPi * k * gxh[ix] / 16.0));
+        tc[ix * 16 + 6 + k] = (float)(2.0 * std::sin(2 * kPi * k * gxh[ix] / 16.0));
+      }
+      tc[ix * 16 + 14] = (float)std::cos(kPi * gxh[ix]);
+    }
+    if ((e = upload(c, &c->tabB, tb)) != hipSuccess) return e;
+    if ((e = upload(c, &c->tabC, tc)) != hipSuccess) return e;
+  }
   std::vector<float> gx(gxh, gxh + c->nvx), gy(gyh, gyh + c->nvy);
   if ((e = upload(c, &c->gx, gx)) != hipSuccess) return e;
   if ((e = upload(c, &c->gy, gy)) != hipSuccess) return e;
@@ -196,6 +219,7 @@ void rmdf_params_default(rmdf_params* p) {
   p->fixed_vx = p->fixed_vy = 0.0f;
   p->conf_threshold = 0.9f;
   p->tile_rows = 0;
+  p->kernel_variant = 0;
 }
 
 rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid_x, int nvx, const float* vgrid_y,
@@ -230,6 +254,10 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   if (p.velocity_mode == RMDF_VEL_FIXED && !(std::isfinite(p.fixed_vx) && std::isfinite(p.fixed_vy)))
     return fail(nullptr, RMDF_E_INVAL, "fixed velocity must be finite");
   if (p.tile_rows < 0) return fail(nullptr, RMDF_E_INVAL, "tile_rows must be >= 0");
+  if (p.kernel_variant < 0 || p.kernel_variant > 2) return fail(nullptr, RMDF_E_INVAL, "kernel_variant must be 0, 1 or 2");
+  const bool w16 = rmdf::pixel16_eligible(Kx, Ky, Kt, nvx, nvy);
+  if (p.kernel_variant == 2 && !w16)
+    return fail(nullptr, RMDF_E_UNSUPPORTED, "kernel_variant 2 needs a 16x16x8 window and at most 21 candidates per axis");
   if (!rmdf::shape_supported(Kx, Ky, Kt))
     return fail(nullptr, RMDF_E_UNSUPPORTED, "window shape has no compiled kernel (8x8x4, 16x16x8, 9x9x5)");
 
@@ -248,6 +276,7 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   c->alpha = alpha; c->vmode = p.velocity_mode; c->fvx = p.fixed_vx; c->fvy = p.fixed_vy;
   c->conf = p.conf_threshold;
   c->TY = p.tile_rows > 0 ? p.tile_rows : 32;
+  c->variant = p.kernel_variant != 0 ? p.kernel_variant : (w16 ? 2 : 1);
   c->nring = dt + 1;
   // NULL: the device's default (null) stream, which is also torch's default
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -320,9 +349,9 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
   a.out = c->out; a.vxy = c->vxy; a.vidx = c->vidx;
   a.twy = c->twy; a.twz = c->twz; a.twA = c->twA; a.tauy = c->tauy; a.taux = c->taux; a.htab = c->htab;
-  a.gx = c->gx; a.gy = c->gy;
+  a.gx = c->gx; a.gy = c->gy; a.tabB = c->tabB; a.tabC = c->tabC;
   timed_begin(c, 0, &ev);
-  e = rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
+  e = (c->variant == 2) ? rmdf::launch_pixel16(a, c->stream) : rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
   timed_end(c, &ev);
   if (e != hipSuccess) return hip_fail(c, e, "pixel kernel launch");
   c->t += 1;

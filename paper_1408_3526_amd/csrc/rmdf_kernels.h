@@ -33,6 +33,8 @@ struct PixArgs {
   const float2* htab;          // [nv+1][bx+1][2by+1][Mz] background coefficients
   const float* gx;             // [nvx]
   const float* gy;             // [nvy]
+  const float* tabB;           // [nvy][16] cos/sin(2 pi k l_y / 16), k = 1..7; cos(pi l_y)
+  const float* tabC;           // [nvx][16] 2cos/2sin(2 pi k l_x / 16), k = 1..7; cos(pi l_x)
 };
 
 bool shape_supported(int mx, int my, int mz);
@@ -41,6 +43,8 @@ hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s)
 hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s);
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
                            hipStream_t s);
+bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
+hipError_t launch_pixel16(const PixArgs& a, hipStream_t s);
 hipError_t launch_ingest(const float* in, float* slot, long long n, unsigned long long* nonfinite, hipStream_t s);
 
 }  // namespace rmdf

@@ -133,14 +133,16 @@ def test_parity_ragged_8x8x4(orc, H, W, tile):
     check_velocity_and_output(gres, r, fr, len(g), g, g)
 
 
-def test_parity_window_16x16x8_flow(orc):
+@pytest.mark.parametrize("variant", [1, 2])
+def test_parity_window_16x16x8_flow(orc, variant):
     """16x16x8 window, 17x17 grid at 0.5 px/frame, non-uniform flow with an
-    occluding band and targets; several row tiles with a ragged tail."""
+    occluding band and targets; several row tiles with a ragged tail; both
+    per-pixel kernels (generic LDS-staged, one wavefront per anchor)."""
     sc = scenes.flow_scene(5, H=40, W=47, T=12, n_targets=3, band_width=(8, 12))
     g = scenes.grid(-4, 4, 0.5)
     M = (16, 16, 8)
     xs, ys = np.array([0, 46, 20, 15, 46]), np.array([0, 39, 20, 33, 0])
-    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), tile_rows=16)
+    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), tile_rows=16, kernel_variant=variant)
     r = orc.run(_cfg(orc, 40, 47, M, g, g), sc.frames, want_rs=True, want_spec=True)
     check_spec(gres, r, xs, ys)
     check_rs(gres, r)
