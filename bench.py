@@ -73,6 +73,7 @@ def main():
     ap.add_argument("--workload", default="640x512", choices=sorted(WORKLOADS))
     ap.add_argument("--frames", type=int, default=0, help="distinct synthetic frames (0: workload default)")
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 generic, 2 wave-per-anchor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -98,7 +99,7 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.from_numpy(frames).cuda()
     T = dev.shape[0]
-    f = binding.Filter(H, W, *M, g, g, tile_rows=args.tile_rows)
+    f = binding.Filter(H, W, *M, g, g, tile_rows=args.tile_rows, kernel_variant=args.kernel_variant)
     stream = torch.cuda.current_stream()
 
     for i in range(args.warmup):
@@ -147,7 +148,7 @@ def main():
                    "frames_distinct": int(T), "tile_rows": args.tile_rows or 32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_pixel<%d,%d,%d>" % M, "kernel_ms": pix_ms,
+                     "kernel": f.kernel_name(), "kernel_ms": pix_ms,
                      "algorithmic_bytes_per_pixel_frame": bpp},
         "kernel_ms": {"pixel": pix_ms, "row": kms[1][0] / max(kms[1][1], 1), "ingest": kms[2][0] / max(kms[2][1], 1)},
         "wall_s": wall,

@@ -131,6 +131,10 @@ rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);
 rmdf_status rmdf_set_timing(rmdf_ctx *ctx, int on);
 rmdf_status rmdf_kernel_time(rmdf_ctx *ctx, int which, double *ms, long long *launches);
 
+/* Per-pixel kernel variant the context launches (1 generic, 2 one wavefront
+ * per anchor), after resolving kernel_variant = 0. */
+rmdf_status rmdf_kernel_variant(const rmdf_ctx *ctx, int *variant);
+
 /* Bytes of device memory the context holds. */
 rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);
 

@@ -56,6 +56,7 @@ _SIGS = {
     "rmdf_set_timing": (_I, [_VP, _I]),
     "rmdf_kernel_time": (_I, [_VP, _I, ctypes.POINTER(_D), ctypes.POINTER(_LL)]),
     "rmdf_device_bytes": (_I, [_VP, ctypes.POINTER(_SZ)]),
+    "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
 }
@@ -211,6 +212,13 @@ class Filter:
         ms, n = ctypes.c_double(), ctypes.c_longlong()
         _check(lib().rmdf_kernel_time(self.ctx, int(which), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
         return ms.value, n.value
+
+    def kernel_name(self) -> str:
+        """Name of the per-pixel kernel this context launches."""
+        v = ctypes.c_int()
+        _check(lib().rmdf_kernel_variant(self.ctx, ctypes.byref(v)), self.ctx)
+        Mx, My, Mz = self.M
+        return "k_pixel16" if v.value == 2 else "k_pixel<%d,%d,%d>" % (Mx, My, Mz)
 
     def frames_pushed(self) -> int:
         n = ctypes.c_longlong()

@@ -457,6 +457,12 @@ rmdf_status rmdf_kernel_time(rmdf_ctx* c, int which, double* ms, long long* laun
   return RMDF_OK;
 }
 
+rmdf_status rmdf_kernel_variant(const rmdf_ctx* c, int* variant) {
+  if (!c || !variant) return RMDF_E_INVAL;
+  *variant = c->variant;
+  return RMDF_OK;
+}
+
 rmdf_status rmdf_device_bytes(const rmdf_ctx* c, size_t* bytes) {
   if (!c || !bytes) return RMDF_E_INVAL;
   *bytes = c->bytes;
