@@ -123,6 +123,7 @@ def main():
     f.set_timing(False)
     out = f.output()
     assert torch.isfinite(out).all()
+    kname = f.kernel_name()
     f.close()
 
     px_frames = args.steps * H * W
@@ -148,7 +149,7 @@ def main():
                    "frames_distinct": int(T), "tile_rows": args.tile_rows or 32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f.kernel_name(), "kernel_ms": pix_ms,
+                     "kernel": kname, "kernel_ms": pix_ms,
                      "algorithmic_bytes_per_pixel_frame": bpp},
         "kernel_ms": {"pixel": pix_ms, "row": kms[1][0] / max(kms[1][1], 1), "ingest": kms[2][0] / max(kms[2][1], 1)},
         "wall_s": wall,

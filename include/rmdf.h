@@ -141,6 +141,52 @@ rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);
 /* Free everything; ctx may be NULL. */
 rmdf_status rmdf_destroy(rmdf_ctx *ctx);
 
+/* ---- Many streams in one step -------------------------------------------
+ * Independent sensor streams, each with its own frame size, window and
+ * candidate grid, advanced together one frame per step.  A step is one
+ * hipGraph launch of two kernels: the row sliding DFT of every stream, then a
+ * persistent per-pixel kernel whose workgroups pull (stream, tile) items from
+ * a queue ordered by decreasing cost.  Window shapes and velocity modes as for
+ * rmdf_create (search or fixed). */
+typedef struct rmdf_batch rmdf_batch;
+typedef struct {
+  int H, W, Kx, Ky, Kt;              /* frame size and window lengths         */
+  const float *vgrid_x, *vgrid_y;    /* host candidate grids (copied)         */
+  int nvx, nvy;
+} rmdf_stream_desc;
+
+/* Create n streams (p applies to all; NULL: defaults).  hip_stream: stream to
+ * run on; NULL creates one (a captured graph cannot run on the null stream).
+ * Errors as rmdf_create, reported for the first failing stream. */
+rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc *streams, const rmdf_params *p,
+                              void *hip_stream, rmdf_batch **out);
+/* Device address where the next frame of stream s (H*W FP32) must be written
+ * before rmdf_batch_launch (zero-copy input). */
+rmdf_status rmdf_batch_input(rmdf_batch *b, int s, float **frame_dev);
+/* Advance every stream by one frame (one graph launch). */
+rmdf_status rmdf_batch_launch(rmdf_batch *b);
+/* Copy frames_dev[s] (n device pointers) into the input slots, then launch. */
+rmdf_status rmdf_batch_push(rmdf_batch *b, const float *const *frames_dev);
+/* Latest output / velocity / index of stream s (any may be NULL). */
+rmdf_status rmdf_batch_output(rmdf_batch *b, int s, float *out_dev, float *vxy_dev, int *idx_dev);
+/* The single-stream view of stream s (for rmdf_spectrum, rmdf_smoothed_r...);
+ * owned by the batch, do not destroy it or push frames through it. */
+rmdf_status rmdf_batch_stream_ctx(rmdf_batch *b, int s, rmdf_ctx **ctx);
+/* Rows per work tile for stream s (s = -1: all); rebuilds the graph. */
+rmdf_status rmdf_batch_set_tiles(rmdf_batch *b, int s, int tile_rows);
+/* Pick rows per tile for each size class and the persistent grid size by
+ * timing whole steps (iters timed launches per candidate).  The streams
+ * advance while tuning (whatever the input slots hold is consumed).  A text
+ * summary goes to report (may be NULL). */
+rmdf_status rmdf_batch_autotune(rmdf_batch *b, int iters, char *report, size_t report_len);
+/* Per-step latency (HIP events around each graph launch while timing is on):
+ * median, 99th percentile and mean in ms over the launches since the last
+ * call; synchronises the stream. */
+rmdf_status rmdf_batch_set_timing(rmdf_batch *b, int on);
+rmdf_status rmdf_batch_latency(rmdf_batch *b, float *p50_ms, float *p99_ms, float *mean_ms, long long *n);
+rmdf_status rmdf_batch_destroy(rmdf_batch *b);
+const char *rmdf_batch_last_error(const rmdf_batch *b);
+
 /* Message of the last error on ctx (NULL ctx: the calling thread's last
  * rmdf_create error).  Never NULL. */
 const char *rmdf_last_error(const rmdf_ctx *ctx);

@@ -59,7 +59,26 @@ _SIGS = {
     "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
+    "rmdf_batch_create": (_I, [_I, _VP, ctypes.POINTER(rmdf_params), _VP, ctypes.POINTER(_VP)]),
+    "rmdf_batch_input": (_I, [_VP, _I, ctypes.POINTER(_VP)]),
+    "rmdf_batch_launch": (_I, [_VP]),
+    "rmdf_batch_push": (_I, [_VP, _VP]),
+    "rmdf_batch_output": (_I, [_VP, _I, _VP, _VP, _VP]),
+    "rmdf_batch_stream_ctx": (_I, [_VP, _I, ctypes.POINTER(_VP)]),
+    "rmdf_batch_set_tiles": (_I, [_VP, _I, _I]),
+    "rmdf_batch_autotune": (_I, [_VP, _I, ctypes.c_char_p, _SZ]),
+    "rmdf_batch_set_timing": (_I, [_VP, _I]),
+    "rmdf_batch_latency": (_I, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_LL)]),
+    "rmdf_batch_destroy": (_I, [_VP]),
+    "rmdf_batch_last_error": (ctypes.c_char_p, [_VP]),
 }
+
+
+class rmdf_stream_desc(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int), ("W", ctypes.c_int), ("Kx", ctypes.c_int), ("Ky", ctypes.c_int),
+                ("Kt", ctypes.c_int), ("vgrid_x", ctypes.c_void_p), ("vgrid_y", ctypes.c_void_p),
+                ("nvx", ctypes.c_int), ("nvy", ctypes.c_int)]
 
 
 def lib():
@@ -85,6 +104,12 @@ def exported_names():
 def _check(status: int, ctx=None):
     if status != RMDF_OK:
         msg = lib().rmdf_last_error(ctx)
+        raise RmdfError(status, msg.decode() if msg else "")
+
+
+def _bcheck(status: int, b=None):
+    if status != RMDF_OK:
+        msg = lib().rmdf_batch_last_error(b)
         raise RmdfError(status, msg.decode() if msg else "")
 
 
@@ -251,3 +276,94 @@ class Filter:
 
     def __exit__(self, *exc):
         self.close()
+
+
+class Batch:
+    """Many independent streams advanced together (one hipGraph launch per
+    step).  ``streams`` is a list of dicts with H, W, M=(Kx, Ky, Kt), gx, gy."""
+
+    def __init__(self, streams, *, tile_rows=0, kernel_variant=0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0),
+                 stream=None):
+        import torch
+        self.specs = []
+        descs = (rmdf_stream_desc * len(streams))()
+        self._keep = []
+        for i, sp in enumerate(streams):
+            gx = np.ascontiguousarray(sp["gx"], np.float32)
+            gy = np.ascontiguousarray(sp["gy"], np.float32)
+            self._keep += [gx, gy]
+            Mx, My, Mz = sp["M"]
+            descs[i] = rmdf_stream_desc(int(sp["H"]), int(sp["W"]), Mx, My, Mz, gx.ctypes.data, gy.ctypes.data,
+                                        len(gx), len(gy))
+            self.specs.append(dict(sp, nv=len(gx) * len(gy)))
+        p = rmdf_params_default()
+        p.tile_rows = int(tile_rows)
+        p.kernel_variant = int(kernel_variant)
+        p.velocity_mode = int(velocity_mode)
+        p.fixed_vx, p.fixed_vy = (float(v) for v in fixed_v)
+        if stream is None:
+            self.torch_stream = torch.cuda.Stream()
+            stream = self.torch_stream.cuda_stream
+        self.stream_handle = int(stream)
+        self.b = _VP()
+        _bcheck(lib().rmdf_batch_create(len(streams), descs, ctypes.byref(p), ctypes.c_void_p(self.stream_handle),
+                                        ctypes.byref(self.b)), None)
+        self.n = len(streams)
+
+    def input(self, s: int):
+        """Device address of stream s's next input frame (H*W FP32)."""
+        ptr = _VP()
+        _bcheck(lib().rmdf_batch_input(self.b, int(s), ctypes.byref(ptr)), self.b)
+        return ptr.value
+
+    def launch(self):
+        _bcheck(lib().rmdf_batch_launch(self.b), self.b)
+
+    def push(self, frames):
+        import torch
+        ptrs = (ctypes.c_void_p * self.n)()
+        for i, fr in enumerate(frames):
+            sp = self.specs[i]
+            ptrs[i] = _dev_ptr(fr, torch.float32, sp["H"] * sp["W"], "frame %d" % i)
+        _bcheck(lib().rmdf_batch_push(self.b, ptrs), self.b)
+
+    def output(self, s: int):
+        import torch
+        sp = self.specs[s]
+        out = torch.empty((sp["H"], sp["W"]), dtype=torch.float32, device="cuda")
+        vxy = torch.empty((sp["H"], sp["W"], 2), dtype=torch.float32, device="cuda")
+        idx = torch.empty((sp["H"], sp["W"]), dtype=torch.int32, device="cuda")
+        _bcheck(lib().rmdf_batch_output(self.b, int(s), out.data_ptr(), vxy.data_ptr(), idx.data_ptr()), self.b)
+        return out, vxy, idx
+
+    def set_tiles(self, s: int, tile_rows: int):
+        _bcheck(lib().rmdf_batch_set_tiles(self.b, int(s), int(tile_rows)), self.b)
+
+    def autotune(self, iters: int = 5) -> str:
+        buf = ctypes.create_string_buffer(4096)
+        _bcheck(lib().rmdf_batch_autotune(self.b, int(iters), buf, 4096), self.b)
+        return buf.value.decode()
+
+    def set_timing(self, on: bool):
+        _bcheck(lib().rmdf_batch_set_timing(self.b, int(bool(on))), self.b)
+
+    def latency(self):
+        p50, p99, mean, n = ctypes.c_float(), ctypes.c_float(), ctypes.c_float(), ctypes.c_longlong()
+        _bcheck(lib().rmdf_batch_latency(self.b, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(mean),
+                                         ctypes.byref(n)), self.b)
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "mean_ms": mean.value, "steps": n.value}
+
+    def synchronize(self):
+        import torch
+        torch.cuda.synchronize()
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().rmdf_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

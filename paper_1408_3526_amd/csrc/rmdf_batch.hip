@@ -1,0 +1,489 @@
+// rmdf_batch.hip - many independent sensor streams (uneven frame sizes and
+// windows) advanced one frame per step by two kernels captured in a hipGraph:
+//   k_row_batch        row sliding DFT of every stream (one block per
+//                      (stream, row, chunk)); reads each stream's raw frame from
+//                      its delay-ring slot, non-finite samples read as 0
+//   k_batch_persistent one persistent workgroup per resident slot pulls
+//                      (stream, tile) items from an atomic queue ordered by
+//                      decreasing cost and runs that stream's per-pixel tile;
+//                      the last workgroup to finish advances every stream's
+//                      frame counter and re-arms the queue for the next step
+// Nothing in the graph changes between steps: frame counters live in device
+// memory and frames are written into the ring slots before each launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rmdf.h"
+#include "rmdf_device.h"
+#include "rmdf_internal.h"
+#include "rmdf_pixel16.h"
+
+namespace rmdf {
+
+enum : int { KIND_884 = 0, KIND_995 = 1, KIND_16G = 2, KIND_16W = 3 };
+
+struct RowDesc {
+  const float* ring;                 // stream's delay ring
+  float2* rs;                        // row spectra
+  const float2* twx;
+  unsigned long long* nonfinite;
+  long long hw;                      // H * W
+  int H, W, MX, nring;
+  int chunks;                        // row chunks per row
+  int item_base;                     // first block index of this stream
+};
+
+struct BatchPixDesc {
+  PixArgs a;                         // static fields; ring_delayed filled per step
+  const float* ring;
+  long long hw;
+  int nring, dt, kind;
+};
+
+struct BatchState {
+  long long* t;                      // [n] frames pushed per stream (device)
+  unsigned int* queue;               // next work item
+  unsigned int* done;                // finished workgroups
+};
+
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+constexpr size_t ROW_SMEM = cmax(cmax(RowShape<8>::SMEM, RowShape<16>::SMEM), RowShape<9>::SMEM);
+constexpr size_t PIX_SMEM = cmax(cmax(cmax(Shape<8, 8, 4>::SMEM, Shape<9, 9, 5>::SMEM), Shape<16, 16, 8>::SMEM),
+                                 p16::SMEM16);
+
+__global__ void __launch_bounds__(256) k_row_batch(const RowDesc* __restrict__ d, int n, const long long* __restrict__ t) {
+  __shared__ __align__(16) char smem[ROW_SMEM];
+  int s = 0;
+  while (s + 1 < n && (int)blockIdx.x >= d[s + 1].item_base) ++s;   // wave-uniform scan (n is small)
+  const RowDesc& r = d[s];
+  const int local = blockIdx.x - r.item_base;
+  const int y = local / r.chunks, x0 = (local % r.chunks) * RCX;
+  const float* f = r.ring + (size_t)(t[s] % r.nring) * r.hw;
+  if (r.MX == 8) row_chunk<8>(f, r.rs, r.twx, r.H, r.W, y, x0, smem, r.nonfinite);
+  else if (r.MX == 16) row_chunk<16>(f, r.rs, r.twx, r.H, r.W, y, x0, smem, r.nonfinite);
+  else row_chunk<9>(f, r.rs, r.twx, r.H, r.W, y, x0, smem, r.nonfinite);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+k_batch_persistent(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items, int n_streams,
+                   BatchState bs) {
+  __shared__ __align__(16) char smem[PIX_SMEM];
+  __shared__ unsigned int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(bs.queue, 1u);
+    __syncthreads();
+    const unsigned int it = s_item;
+    __syncthreads();                    // all have read s_item before it is overwritten
+    if (it >= (unsigned int)n_items) break;
+    const int4 w = items[it];
+    const BatchPixDesc& bd = d[w.x];
+    const long long tt = bs.t[w.x];
+    const float* rd = (tt >= bd.dt) ? bd.ring + (size_t)((tt - bd.dt) % bd.nring) * bd.hw : nullptr;
+    switch (bd.kind) {
+      case KIND_884: pixel_tile<8, 8, 4>(bd.a, rd, w.y, w.z, smem); break;
+      case KIND_995: pixel_tile<9, 9, 5>(bd.a, rd, w.y, w.z, smem); break;
+      case KIND_16G: pixel_tile<16, 16, 8>(bd.a, rd, w.y, w.z, smem); break;
+      default: p16::pixel16_tile(bd.a, rd, w.y, w.z, smem); break;
+    }
+  }
+  // the last workgroup out advances the frame counters and re-arms the queue
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int prev = atomicAdd(bs.done, 1u);
+    if (prev == gridDim.x - 1) {
+      for (int s = 0; s < n_streams; ++s) bs.t[s] += 1;
+      *bs.queue = 0u;
+      *bs.done = 0u;
+      __threadfence();
+    }
+  }
+}
+
+// Zeroes the queue and completion counters (a kernel, not a memset, so the
+// same code is safe to capture).
+__global__ void k_batch_arm(BatchState bs) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *bs.queue = 0u;
+    *bs.done = 0u;
+  }
+}
+
+}  // namespace rmdf
+
+using namespace rmdf;
+
+struct rmdf_batch {
+  int n = 0;
+  std::vector<rmdf_ctx*> ctx;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::vector<int> tile_rows;        // per stream
+  int grid_mult = 1;                 // persistent workgroups per resident slot
+  int persistent_blocks = 0;
+  // device
+  RowDesc* d_row = nullptr;
+  BatchPixDesc* d_pix = nullptr;
+  int4* d_items = nullptr;
+  long long* d_t = nullptr;
+  unsigned int* d_queue = nullptr;
+  unsigned int* d_done = nullptr;
+  int n_items = 0, row_blocks = 0;
+  std::vector<long long> t;          // host mirror of the frame counters
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<float> lat_ms;
+  std::string err;
+};
+
+static rmdf_status bfail(rmdf_batch* b, rmdf_status s, const std::string& m) {
+  if (b) b->err = m;
+  else rmdf_internal_set_create_error(m);
+  return s;
+}
+
+static int kind_of(const rmdf_ctx* c) {
+  int mx, my, mz, variant;
+  rmdf_internal_shape(c, &mx, &my, &mz, &variant);
+  if (mx == 8) return KIND_884;
+  if (mx == 9) return KIND_995;
+  return variant == 2 ? KIND_16W : KIND_16G;
+}
+
+static void free_graph(rmdf_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Work items and the captured graph for the current tile choice.
+static hipError_t rebuild(rmdf_batch* b) {
+  hipError_t e;
+  free_graph(b);
+  struct Item { int4 w; double cost; };
+  std::vector<Item> items;
+  std::vector<BatchPixDesc> pd(b->n);
+  for (int s = 0; s < b->n; ++s) {
+    rmdf_ctx* c = b->ctx[s];
+    PixArgs a = rmdf_internal_pixargs(c);
+    a.TY = b->tile_rows[s];
+    BatchPixDesc& d = pd[s];
+    d.a = a;
+    d.kind = kind_of(c);
+    d.ring = rmdf_internal_ring(c, &d.nring, &d.dt);
+    d.hw = (long long)a.H * a.W;
+    const int cols = (d.kind == KIND_16W) ? 4 : (d.kind == KIND_884 ? 8 : (d.kind == KIND_995 ? 4 : 2));
+    const int xblocks = (a.W + cols - 1) / cols, yblocks = (a.H + a.TY - 1) / a.TY;
+    int mx, my, mz, v;
+    rmdf_internal_shape(c, &mx, &my, &mz, &v);
+    const double per_px = 8.0 * mx * my * mz + 8.0 * a.nv;
+    for (int yb = 0; yb < yblocks; ++yb)
+      for (int xb = 0; xb < xblocks; ++xb) {
+        const int rows = std::min(a.TY, a.H - yb * a.TY), colsn = std::min(cols, a.W - xb * cols);
+        items.push_back({make_int4(s, xb, yb, 0), per_px * rows * colsn});
+      }
+  }
+  // longest first, so the tail of the step is made of small items
+  std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) { return p.cost > q.cost; });
+  std::vector<int4> iv(items.size());
+  for (size_t i = 0; i < items.size(); ++i) iv[i] = items[i].w;
+  if (b->d_items) hipFree(b->d_items);
+  b->d_items = nullptr;
+  if ((e = hipMalloc(&b->d_items, sizeof(int4) * std::max<size_t>(iv.size(), 1))) != hipSuccess) return e;
+  if ((e = hipMemcpy(b->d_items, iv.data(), sizeof(int4) * iv.size(), hipMemcpyHostToDevice)) != hipSuccess) return e;
+  if ((e = hipMemcpy(b->d_pix, pd.data(), sizeof(BatchPixDesc) * b->n, hipMemcpyHostToDevice)) != hipSuccess) return e;
+  b->n_items = (int)iv.size();
+
+  int dev = 0, cus = 0, occ = 0;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_batch_persistent), 256, 0);
+  b->persistent_blocks = std::max(1, std::min(b->n_items, cus * std::max(occ, 1) * b->grid_mult));
+
+  BatchState bs{b->d_t, b->d_queue, b->d_done};
+  if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_row_batch, dim3(b->row_blocks), dim3(256), 0, b->stream, b->d_row, b->n,
+                     (const long long*)b->d_t);
+  hipLaunchKernelGGL(k_batch_persistent, dim3(b->persistent_blocks), dim3(256), 0, b->stream, b->d_pix,
+                     (const int4*)b->d_items, b->n_items, b->n, bs);
+  if ((e = hipStreamEndCapture(b->stream, &b->graph)) != hipSuccess) return e;
+  if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+extern "C" {
+
+rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_params* p, void* hip_stream,
+                              rmdf_batch** out) {
+  if (!out) return bfail(nullptr, RMDF_E_INVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 4096 || !sd) return bfail(nullptr, RMDF_E_INVAL, "need 1..4096 stream descriptors");
+  rmdf_batch* b = new rmdf_batch();
+  b->n = n;
+  hipError_t e;
+  if (hip_stream) {
+    b->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    // graph capture needs a real stream (the null stream cannot be captured)
+    if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) {
+      delete b;
+      return bfail(nullptr, RMDF_E_DEVICE, "stream creation failed");
+    }
+    b->own_stream = true;
+  }
+  auto bail = [&](rmdf_status st, const std::string& m) {
+    for (auto* c : b->ctx) rmdf_destroy(c);
+    if (b->own_stream) hipStreamDestroy(b->stream);
+    delete b;
+    return bfail(nullptr, st, m);
+  };
+  std::vector<RowDesc> rd(n);
+  int base = 0;
+  for (int s = 0; s < n; ++s) {
+    rmdf_ctx* c = nullptr;
+    rmdf_status st = rmdf_create(sd[s].H, sd[s].W, sd[s].Kx, sd[s].Ky, sd[s].Kt, sd[s].vgrid_x, sd[s].nvx,
+                                 sd[s].vgrid_y, sd[s].nvy, p, b->stream, &c);
+    if (st != RMDF_OK) return bail(st, std::string("stream ") + std::to_string(s) + ": " + rmdf_last_error(nullptr));
+    if (p && p->velocity_mode != RMDF_VEL_SEARCH && p->velocity_mode != RMDF_VEL_FIXED)
+      return bail(RMDF_E_UNSUPPORTED, "batched streams support the search and fixed velocity modes");
+    b->ctx.push_back(c);
+    PixArgs a = rmdf_internal_pixargs(c);
+    b->tile_rows.push_back(a.TY);
+    int nring, dt;
+    RowDesc& r = rd[s];
+    r.ring = rmdf_internal_ring(c, &nring, &dt);
+    r.nring = nring;
+    r.rs = const_cast<float2*>(a.rs);
+    r.twx = rmdf_internal_twx(c);
+    r.nonfinite = rmdf_internal_nonfinite(c);
+    r.H = a.H;
+    r.W = a.W;
+    int mx, my, mz, v;
+    rmdf_internal_shape(c, &mx, &my, &mz, &v);
+    r.MX = mx;
+    r.hw = (long long)a.H * a.W;
+    r.chunks = (a.W + RCX - 1) / RCX;
+    r.item_base = base;
+    base += r.chunks * a.H;
+  }
+  b->row_blocks = base;
+  b->t.assign(n, 0);
+  if ((e = hipMalloc(&b->d_row, sizeof(RowDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
+  if ((e = hipMalloc(&b->d_pix, sizeof(BatchPixDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
+  if ((e = hipMalloc(&b->d_t, sizeof(long long) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
+  if ((e = hipMalloc(&b->d_queue, sizeof(unsigned int))) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
+  if ((e = hipMalloc(&b->d_done, sizeof(unsigned int))) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
+  hipMemcpy(b->d_row, rd.data(), sizeof(RowDesc) * n, hipMemcpyHostToDevice);
+  hipMemcpy(b->d_t, b->t.data(), sizeof(long long) * n, hipMemcpyHostToDevice);
+  hipLaunchKernelGGL(k_batch_arm, dim3(1), dim3(64), 0, b->stream, BatchState{b->d_t, b->d_queue, b->d_done});
+  if ((e = rebuild(b)) != hipSuccess) return bail(RMDF_E_DEVICE, std::string("graph: ") + hipGetErrorString(e));
+  if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return bail(RMDF_E_DEVICE, "sync");
+  *out = b;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_input(rmdf_batch* b, int s, float** frame_dev) {
+  if (!b || !frame_dev || s < 0 || s >= b->n) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  int nring, dt;
+  float* ring = const_cast<float*>(rmdf_internal_ring(b->ctx[s], &nring, &dt));
+  const PixArgs a = rmdf_internal_pixargs(b->ctx[s]);
+  *frame_dev = ring + (size_t)(b->t[s] % nring) * (size_t)a.H * a.W;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_launch(rmdf_batch* b) {
+  if (!b) return bfail(nullptr, RMDF_E_INVAL, "batch is NULL");
+  hipError_t e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (b->timing) {
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    hipEventRecord(e0, b->stream);
+  }
+  if ((e = hipGraphLaunch(b->exec, b->stream)) != hipSuccess) return bfail(b, RMDF_E_DEVICE, hipGetErrorString(e));
+  if (b->timing) {
+    hipEventRecord(e1, b->stream);
+    b->ev.emplace_back(e0, e1);
+  }
+  for (int s = 0; s < b->n; ++s) {
+    b->t[s] += 1;
+    rmdf_internal_advance(b->ctx[s]);
+  }
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_push(rmdf_batch* b, const float* const* frames) {
+  if (!b || !frames) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  for (int s = 0; s < b->n; ++s) {
+    if (!frames[s]) return bfail(b, RMDF_E_INVAL, "NULL frame pointer");
+    float* dst = nullptr;
+    rmdf_batch_input(b, s, &dst);
+    const PixArgs a = rmdf_internal_pixargs(b->ctx[s]);
+    hipError_t e = hipMemcpyAsync(dst, frames[s], sizeof(float) * (size_t)a.H * a.W, hipMemcpyDeviceToDevice, b->stream);
+    if (e != hipSuccess) return bfail(b, RMDF_E_DEVICE, hipGetErrorString(e));
+  }
+  return rmdf_batch_launch(b);
+}
+
+rmdf_status rmdf_batch_output(rmdf_batch* b, int s, float* out, float* vxy, int* idx) {
+  if (!b || s < 0 || s >= b->n) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  rmdf_status st = RMDF_OK;
+  if (out) st = rmdf_output(b->ctx[s], out);
+  if (st == RMDF_OK && (vxy || idx)) st = rmdf_velocity(b->ctx[s], vxy, idx);
+  if (st != RMDF_OK) return bfail(b, st, rmdf_last_error(b->ctx[s]));
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_stream_ctx(rmdf_batch* b, int s, rmdf_ctx** ctx) {
+  if (!b || !ctx || s < 0 || s >= b->n) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  *ctx = b->ctx[s];
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_set_tiles(rmdf_batch* b, int s, int tile_rows) {
+  if (!b || s < -1 || s >= b->n || tile_rows < 1) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  hipStreamSynchronize(b->stream);
+  for (int i = 0; i < b->n; ++i)
+    if (s < 0 || i == s) b->tile_rows[i] = tile_rows;
+  hipError_t e = rebuild(b);
+  if (e != hipSuccess) return bfail(b, RMDF_E_DEVICE, hipGetErrorString(e));
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_set_timing(rmdf_batch* b, int on) {
+  if (!b) return bfail(nullptr, RMDF_E_INVAL, "batch is NULL");
+  b->timing = on != 0;
+  return RMDF_OK;
+}
+
+static void collect(rmdf_batch* b) {
+  hipStreamSynchronize(b->stream);
+  for (auto& pr : b->ev) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, pr.first, pr.second);
+    b->lat_ms.push_back(ms);
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  b->ev.clear();
+}
+
+rmdf_status rmdf_batch_latency(rmdf_batch* b, float* p50, float* p99, float* mean, long long* n) {
+  if (!b || !p50 || !p99 || !mean || !n) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  collect(b);
+  std::vector<float> v = b->lat_ms;
+  b->lat_ms.clear();
+  *n = (long long)v.size();
+  if (v.empty()) { *p50 = *p99 = *mean = 0.f; return RMDF_OK; }
+  std::sort(v.begin(), v.end());
+  auto pct = [&](double q) { return v[std::min(v.size() - 1, (size_t)std::floor(q * (v.size() - 1) + 0.5))]; };
+  *p50 = pct(0.50);
+  *p99 = pct(0.99);
+  double s = 0;
+  for (float x : v) s += x;
+  *mean = (float)(s / v.size());
+  return RMDF_OK;
+}
+
+// Coordinate descent over the rows per work tile of each size class (streams
+// with the same frame size and window), timing whole steps; the frames in the
+// input slots are consumed (the streams advance).
+rmdf_status rmdf_batch_autotune(rmdf_batch* b, int iters, char* report, size_t report_len) {
+  if (!b || iters < 1) return bfail(b, RMDF_E_INVAL, "bad arguments");
+  struct Cls { int H, W, kind; std::vector<int> members; };
+  std::vector<Cls> cls;
+  for (int s = 0; s < b->n; ++s) {
+    const PixArgs a = rmdf_internal_pixargs(b->ctx[s]);
+    const int k = kind_of(b->ctx[s]);
+    auto it = std::find_if(cls.begin(), cls.end(), [&](const Cls& c) { return c.H == a.H && c.W == a.W && c.kind == k; });
+    if (it == cls.end()) cls.push_back({a.H, a.W, k, {s}});
+    else it->members.push_back(s);
+  }
+  const bool was = b->timing;
+  auto measure = [&]() -> float {
+    b->timing = true;
+    collect(b);
+    b->lat_ms.clear();
+    for (int i = 0; i < 2; ++i) rmdf_batch_launch(b);   // warm
+    collect(b);
+    b->lat_ms.clear();
+    for (int i = 0; i < iters; ++i) rmdf_batch_launch(b);
+    collect(b);
+    std::vector<float> v = b->lat_ms;
+    b->lat_ms.clear();
+    std::sort(v.begin(), v.end());
+    return v[v.size() / 2];
+  };
+  const int cand[] = {8, 16, 32, 64};
+  std::string rep;
+  float best_all = measure();
+  for (auto& c : cls) {
+    int best_ty = b->tile_rows[c.members[0]];
+    for (int ty : cand) {
+      if (ty == best_ty) continue;
+      for (int s : c.members) b->tile_rows[s] = ty;
+      if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
+      const float m = measure();
+      if (m < best_all) { best_all = m; best_ty = ty; }
+    }
+    for (int s : c.members) b->tile_rows[s] = best_ty;
+    if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
+    char line[160];
+    std::snprintf(line, sizeof line, "%dx%d kind %d (%zu streams): tile_rows %d\n", c.W, c.H, c.kind,
+                  c.members.size(), best_ty);
+    rep += line;
+  }
+  int best_mult = b->grid_mult;
+  for (int m : {1, 2}) {
+    if (m == best_mult) continue;
+    b->grid_mult = m;
+    if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
+    const float t = measure();
+    if (t < best_all) { best_all = t; best_mult = m; }
+  }
+  b->grid_mult = best_mult;
+  if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
+  char line[160];
+  std::snprintf(line, sizeof line, "persistent workgroups per slot %d; median step %.3f ms\n", best_mult, best_all);
+  rep += line;
+  b->timing = was;
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_destroy(rmdf_batch* b) {
+  if (!b) return RMDF_OK;
+  hipStreamSynchronize(b->stream);
+  for (auto& pr : b->ev) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
+  free_graph(b);
+  hipFree(b->d_items);
+  hipFree(b->d_row);
+  hipFree(b->d_pix);
+  hipFree(b->d_t);
+  hipFree(b->d_queue);
+  hipFree(b->d_done);
+  for (auto* c : b->ctx) rmdf_destroy(c);
+  if (b->own_stream) hipStreamDestroy(b->stream);
+  delete b;
+  return RMDF_OK;
+}
+
+const char* rmdf_batch_last_error(const rmdf_batch* b) {
+  if (!b) return rmdf_last_error(nullptr);
+  return b->err.c_str();
+}
+
+}  // extern "C"

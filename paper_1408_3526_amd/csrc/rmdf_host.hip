@@ -13,6 +13,7 @@
 
 #include "../../include/rmdf.h"
 #include "rmdf_kernels.h"
+#include "rmdf_internal.h"
 
 using cd = std::complex<double>;
 static const double kPi = 3.14159265358979323846264338327950288;
@@ -208,6 +209,34 @@ static hipError_t build_tables(rmdf_ctx* c, const float* gxh, const float* gyh) 
   return hipSuccess;
 }
 
+rmdf::PixArgs rmdf_internal_pixargs(const rmdf_ctx* c) {
+  rmdf::PixArgs a{};
+  a.H = c->H; a.W = c->W; a.TY = c->TY;
+  a.nvx = c->nvx; a.nvy = c->nvy; a.nv = c->nv;
+  a.bx = c->Bx; a.by = c->By; a.dx = c->dx; a.dy = c->dy;
+  a.vmode = c->vmode;
+  a.alpha = c->alpha; a.inv_sqrt_my = (float)(1.0 / std::sqrt((double)c->MY));
+  a.fvx = c->fvx; a.fvy = c->fvy;
+  a.rs = c->rs; a.st = c->st; a.rsm = c->rsm;
+  a.ring_delayed = nullptr;
+  a.out = c->out; a.vxy = c->vxy; a.vidx = c->vidx;
+  a.twy = c->twy; a.twz = c->twz; a.twA = c->twA; a.tauy = c->tauy; a.taux = c->taux; a.htab = c->htab;
+  a.gx = c->gx; a.gy = c->gy; a.tabB = c->tabB; a.tabC = c->tabC;
+  return a;
+}
+const float* rmdf_internal_ring(const rmdf_ctx* c, int* nring, int* dt) {
+  *nring = c->nring;
+  *dt = c->dt;
+  return c->ring;
+}
+const float2* rmdf_internal_twx(const rmdf_ctx* c) { return c->twx; }
+unsigned long long* rmdf_internal_nonfinite(const rmdf_ctx* c) { return c->nonfinite; }
+void rmdf_internal_shape(const rmdf_ctx* c, int* mx, int* my, int* mz, int* variant) {
+  *mx = c->MX; *my = c->MY; *mz = c->MZ; *variant = c->variant;
+}
+void rmdf_internal_advance(rmdf_ctx* c) { c->t += 1; }
+void rmdf_internal_set_create_error(const std::string& m) { g_create_error = m; }
+
 extern "C" {
 
 void rmdf_params_default(rmdf_params* p) {
@@ -338,18 +367,8 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   timed_end(c, &ev);
   if (e != hipSuccess) return hip_fail(c, e, "row kernel launch");
 
-  rmdf::PixArgs a{};
-  a.H = c->H; a.W = c->W; a.TY = c->TY;
-  a.nvx = c->nvx; a.nvy = c->nvy; a.nv = c->nv;
-  a.bx = c->Bx; a.by = c->By; a.dx = c->dx; a.dy = c->dy;
-  a.vmode = c->vmode;
-  a.alpha = c->alpha; a.inv_sqrt_my = (float)(1.0 / std::sqrt((double)c->MY));
-  a.fvx = c->fvx; a.fvy = c->fvy;
-  a.rs = c->rs; a.st = c->st; a.rsm = c->rsm;
+  rmdf::PixArgs a = rmdf_internal_pixargs(c);
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
-  a.out = c->out; a.vxy = c->vxy; a.vidx = c->vidx;
-  a.twy = c->twy; a.twz = c->twz; a.twA = c->twA; a.tauy = c->tauy; a.taux = c->taux; a.htab = c->htab;
-  a.gx = c->gx; a.gy = c->gy; a.tabB = c->tabB; a.tabC = c->tabC;
   timed_begin(c, 0, &ev);
   e = (c->variant == 2) ? rmdf::launch_pixel16(a, c->stream) : rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
   timed_end(c, &ev);

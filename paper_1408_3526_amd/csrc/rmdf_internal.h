@@ -1,0 +1,18 @@
+// rmdf_internal.h - host-side accessors shared by the single-stream context
+// (rmdf_host.hip) and the batched streams (rmdf_batch.hip).  Not part of the
+// public ABI.
+#pragma once
+#include <string>
+
+#include "../../include/rmdf.h"
+#include "rmdf_kernels.h"
+
+// Per-pixel kernel arguments of a context (static fields; ring_delayed unset).
+rmdf::PixArgs rmdf_internal_pixargs(const rmdf_ctx* c);
+const float* rmdf_internal_ring(const rmdf_ctx* c, int* nring, int* dt);
+const float2* rmdf_internal_twx(const rmdf_ctx* c);
+unsigned long long* rmdf_internal_nonfinite(const rmdf_ctx* c);
+void rmdf_internal_shape(const rmdf_ctx* c, int* mx, int* my, int* mz, int* variant);
+// Count one frame pushed by someone else (the batched step).
+void rmdf_internal_advance(rmdf_ctx* c);
+void rmdf_internal_set_create_error(const std::string& m);

@@ -1,393 +1,16 @@
-// rmdf_pixel16.hip - per-pixel kernel specialised for the 16x16x8 window.
-//
-// One wavefront owns one anchor column x and walks down a tile of rows; the
-// four wavefronts of a workgroup are independent (wave-level LDS sync only).
-// Lane (r, ky) = (lane / 16, lane % 16) holds the (plane, ky) columns
-// (r, ky) and (r + 4, ky) of the Hermitian half of the local spectrum
-// (plane 0 packs kx = 0 and kx = 8, see rmdf_kernels.hip), i.e. 2 x 8
-// complex observer states.  Per row:
-//   column sliding DFT        in registers (one resonator per column)
-//   deadbeat observer         in registers; state streamed once (8 KB/pixel
-//                             read + 8 KB written, prefetched one row ahead)
-//   high-pass, Hann along kz  in registers
-//   Hann along ky             DPP row rotations (a row of 16 lanes = one plane)
-//   unpack of kx = 0 / 8      DPP row mirror (the -ky partner) + register (-kz)
-//   Hann along kx, P, stage A LDS exchange of neighbouring planes
-//   stage B (ky -> l_y)       lanes = (kx group, l_y); even/odd split in ky
-//   stage C (kx -> l_x)       lanes = (l_y group, l_x); smoothing; argmax
-//   background estimate       lanes' own columns x coefficient table
-// Trigonometric weights of stages B and C stay in registers for the whole
-// kernel.
+// rmdf_pixel16.hip - launcher of the 16x16x8 wave-per-anchor pixel kernel
+// (the work tile is in rmdf_pixel16.h).
 #include <hip/hip_runtime.h>
 
-#include "rmdf_kernels.h"
+#include "rmdf_pixel16.h"
 
 namespace rmdf {
 namespace p16 {
 
-constexpr int MX = 16, MY = 16, MZ = 8;
-constexpr int NXH = 9;            // kx = 0..8
-constexpr int NCOL = 128;         // 8 planes x 16 ky
-constexpr int WAVES = 4;          // anchors (x) per workgroup
-constexpr int SB_PLANES = 9;      // kx = 0 .. 8
-constexpr int SB_KZ = 10;         // kz slots per (plane, ky) row: 80 B, so a row of 16
-                                  // lanes writing 16 B each covers 64 distinct banks
-constexpr int SB_ELEMS = SB_PLANES * MY * SB_KZ;   // float2 per wave
-constexpr int NV1_MAX = 21;       // 3 lane groups x 21 <= 64
-
-__device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
-
-template <int CTRL>
-__device__ __forceinline__ float dppf(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-// row_ror:n -> dst[i] = src[(i - n) mod 16] within each row of 16 lanes
-constexpr int ROR1 = 0x121, ROR15 = 0x12F;
-
-template <int CTRL>
-__device__ __forceinline__ float2 dpp2(float2 v) { return f2(dppf<CTRL>(v.x), dppf<CTRL>(v.y)); }
-
-// value held by lane (r, -ky mod 16) of the same row
-__device__ __forceinline__ float2 row_neg(float2 v) {
-  const int lane = threadIdx.x & 63;
-  const int src = (lane & 48) | ((16 - (lane & 15)) & 15);
-  return f2(__shfl(v.x, src, 64), __shfl(v.y, src, 64));
-}
-
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// s_b index of (plane kx in [0, 8], ky, kz)
-__device__ __forceinline__ int sb_idx(int kx, int ky, int kz) { return (kx * MY + ky) * SB_KZ + kz; }
-
-// w_8^k X for the eight posterior states (exact rotations for even k)
-__device__ __forceinline__ float2 rot8(float2 a, int k) {
-  const float c = 0.70710678118654752f;
-  switch (k & 7) {
-    case 0: return a;
-    case 1: return f2((a.x - a.y) * c, (a.x + a.y) * c);
-    case 2: return f2(-a.y, a.x);
-    case 3: return f2(-(a.x + a.y) * c, (a.x - a.y) * c);
-    case 4: return f2(-a.x, -a.y);
-    case 5: return f2((a.y - a.x) * c, -(a.x + a.y) * c);
-    case 6: return f2(a.y, -a.x);
-    default: return f2((a.x + a.y) * c, (a.y - a.x) * c);
-  }
-}
-
-__device__ __forceinline__ void amax_merge(float& v, int& i, float v2, int i2) {
-  if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
-}
-
-// sum_kz P_kz w_8^kz / 512 (stage A of the autocorrelation at l_z = 1: the
-// 1/4 per Hann axis and S = sqrt(8) X give P = |h'|^2 * 8 / 4096)
-__device__ __forceinline__ float2 stageA(const float P[MZ]) {
-  const float c = 0.70710678118654752f;
-  const float re = (P[0] - P[4]) + c * (P[1] - P[3] - P[5] + P[7]);
-  const float im = (P[2] - P[6]) + c * (P[1] + P[3] - P[5] - P[7]);
-  return f2(re * (1.0f / 512.0f), im * (1.0f / 512.0f));
-}
-
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pixel16(PixArgs a) {
-  __shared__ float2 s_all[WAVES * SB_ELEMS];
-  __shared__ float4 s_tab[2 * NV1_MAX * 4];     // rows of tabB then tabC (16 floats each)
-  const int lane = threadIdx.x & 63;
-  // wave-uniform values live in scalar registers
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  float2* s_b = s_all + wv * SB_ELEMS;
-  float2* s_q = s_b;                       // [9][16] after Hann along kx
-  float2* s_t = s_b + NXH * MY;            // [9][NV1_MAX]
-  const int nvx = a.nvx, nvy = a.nvy, nv = a.nv;
-  {
-    const float4* tb = reinterpret_cast<const float4*>(a.tabB);
-    const float4* tc = reinterpret_cast<const float4*>(a.tabC);
-    for (int i = threadIdx.x; i < 4 * nvy; i += 256) s_tab[i] = tb[i];
-    for (int i = threadIdx.x; i < 4 * nvx; i += 256) s_tab[4 * NV1_MAX + i] = tc[i];
-  }
-  __syncthreads();                         // the only workgroup barrier
-
+  __shared__ __align__(16) char smem[SMEM16];
   const int xblocks = (a.W + WAVES - 1) / WAVES;
-  const int xb = blockIdx.x % xblocks, yb = blockIdx.x / xblocks;
-  const int x = __builtin_amdgcn_readfirstlane(xb * WAVES + wv);
-  if (x >= a.W) return;                    // whole wavefront leaves
-  const int y0 = yb * a.TY;
-  const int y1 = min(a.H, y0 + a.TY);
-  if (y0 >= y1) return;
-
-  const int r = lane >> 4, ky = lane & 15;
-  const int pA = r, pB = r + 4;
-  // stage B lane (g, iy), stage C lane (h, ix)
-  const int gB = lane / nvy, iyB = lane % nvy;
-  const bool actB = lane < 3 * nvy;
-  const int hC = lane / nvx, ixC = lane % nvx;
-  const bool actC = lane < 3 * nvx;
-  const float2 wy = a.twy[ky];
-
-  const size_t HW = (size_t)a.H * a.W;
-  const float2* rsA = a.rs + (size_t)pA * HW + x;
-  const float2* rsB = a.rs + (size_t)pB * HW + x;
-
-  // column sliding DFT seeded with the 16 rows above the tile (Horner form of
-  // the direct DFT: the same resonator run over those rows)
-  float2 acA = f2(0.f, 0.f), acB = f2(0.f, 0.f);
-  for (int yy = max(0, y0 - MY); yy < y0; ++yy) {
-    const float2 vA = rsA[(size_t)yy * a.W], vB = rsB[(size_t)yy * a.W];
-    acA = f2(wy.x * acA.x - wy.y * acA.y + vA.x, wy.x * acA.y + wy.y * acA.x + vA.y);
-    acB = f2(wy.x * acB.x - wy.y * acB.y + vB.x, wy.x * acB.y + wy.y * acB.x + vB.y);
-  }
-
-  for (int y = y0; y < y1; ++y) {
-    const size_t pix = (size_t)y * a.W + x;
-    // observer state of this anchor (latency is hidden by the other resident
-    // wavefronts; a register prefetch would halve the occupancy)
-    float2 XA[MZ], XB[MZ];
-    {
-      const float2* src = a.st + pix * NCOL * MZ;
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) { XA[k] = src[(pA * MY + ky) * MZ + k]; XB[k] = src[(pB * MY + ky) * MZ + k]; }
-    }
-    // ---- column sliding DFT
-    {
-      float2 iA = rsA[(size_t)y * a.W], iB = rsB[(size_t)y * a.W];
-      if (y >= MY) {
-        const float2 oA = rsA[(size_t)(y - MY) * a.W], oB = rsB[(size_t)(y - MY) * a.W];
-        iA = f2(iA.x - oA.x, iA.y - oA.y);
-        iB = f2(iB.x - oB.x, iB.y - oB.y);
-      }
-      acA = f2(wy.x * acA.x - wy.y * acA.y + iA.x, wy.x * acA.y + wy.y * acA.x + iA.y);
-      acB = f2(wy.x * acB.x - wy.y * acB.y + iB.x, wy.x * acB.y + wy.y * acB.x + iB.y);
-    }
-    // ---- deadbeat observer (posterior rotated, innovation shared by all kz)
-    {
-      float2 sA = f2(0.f, 0.f), sB2 = f2(0.f, 0.f);
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        XA[k] = rot8(XA[k], k);
-        XB[k] = rot8(XB[k], k);
-        sA = f2(sA.x + XA[k].x, sA.y + XA[k].y);
-        sB2 = f2(sB2.x + XB[k].x, sB2.y + XB[k].y);
-      }
-      // s2 = ac / 4 (1/sqrt(16)); e = (s2 - sum) / 8
-      const float2 eA = f2((0.25f * acA.x - sA.x) * 0.125f, (0.25f * acA.y - sA.y) * 0.125f);
-      const float2 eB = f2((0.25f * acB.x - sB2.x) * 0.125f, (0.25f * acB.y - sB2.y) * 0.125f);
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        XA[k] = f2(XA[k].x + eA.x, XA[k].y + eA.y);
-        XB[k] = f2(XB[k].x + eB.x, XB[k].y + eB.y);
-      }
-      float2* dst = a.st + pix * NCOL * MZ;
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) { dst[(pA * MY + ky) * MZ + k] = XA[k]; dst[(pB * MY + ky) * MZ + k] = XB[k]; }
-    }
-    // ---- high-pass + Hann along kz (2X(k) - X(k-1) - X(k+1); the 1/4 per
-    // axis is folded into the stage-A weights)
-    float2 HA[MZ], HB[MZ];
-    {
-      float2 V[MZ];
-      const bool dc = (lane == 0);       // plane 0 (kx = 0 | kx = 8 packed), ky = 0
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const float2 m = XA[(MZ - k) & 7];
-        // drop the kx = 0 part: C - (C + conj C(-kz)) / 2
-        V[k] = dc ? f2(0.5f * (XA[k].x - m.x), 0.5f * (XA[k].y + m.y)) : XA[k];
-      }
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const float2 l = V[(k + 7) & 7], rr = V[(k + 1) & 7];
-        HA[k] = f2(2.f * V[k].x - l.x - rr.x, 2.f * V[k].y - l.y - rr.y);
-        const float2 lb = XB[(k + 7) & 7], rb = XB[(k + 1) & 7];
-        HB[k] = f2(2.f * XB[k].x - lb.x - rb.x, 2.f * XB[k].y - lb.y - rb.y);
-      }
-    }
-    // ---- Hann along ky: the neighbours are the adjacent lanes of the row
-#pragma unroll
-    for (int k = 0; k < MZ; ++k) {
-      const float2 dA = dpp2<ROR1>(HA[k]), uA = dpp2<ROR15>(HA[k]);
-      HA[k] = f2(2.f * HA[k].x - dA.x - uA.x, 2.f * HA[k].y - dA.y - uA.y);
-      const float2 dB = dpp2<ROR1>(HB[k]), uB = dpp2<ROR15>(HB[k]);
-      HB[k] = f2(2.f * HB[k].x - dB.x - uB.x, 2.f * HB[k].y - dB.y - uB.y);
-    }
-    // ---- unpack plane 0: S(0) = (C + conj C(-k)) / 2, S(8) = (C - conj C(-k)) / 2j;
-    // stage the y,z-windowed planes in LDS
-    wave_lds_sync();                     // previous row's stage C reads are done
-    {
-      float2 M[MZ];
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) M[k] = row_neg(HA[k]);
-      if (r == 0) {
-#pragma unroll
-        for (int k = 0; k < MZ; k += 2) {
-          const float2 u0 = HA[k], w0 = M[(MZ - k) & 7], u1 = HA[k + 1], w1 = M[(MZ - k - 1) & 7];
-          *reinterpret_cast<float4*>(&s_b[sb_idx(8, ky, k)]) =
-              make_float4(0.5f * (u0.y + w0.y), -0.5f * (u0.x - w0.x), 0.5f * (u1.y + w1.y), -0.5f * (u1.x - w1.x));
-          HA[k] = f2(0.5f * (u0.x + w0.x), 0.5f * (u0.y - w0.y));
-          HA[k + 1] = f2(0.5f * (u1.x + w1.x), 0.5f * (u1.y - w1.y));
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < MZ; k += 2) {
-      *reinterpret_cast<float4*>(&s_b[sb_idx(pA, ky, k)]) = make_float4(HA[k].x, HA[k].y, HA[k + 1].x, HA[k + 1].y);
-      *reinterpret_cast<float4*>(&s_b[sb_idx(pB, ky, k)]) = make_float4(HB[k].x, HB[k].y, HB[k + 1].x, HB[k + 1].y);
-    }
-    wave_lds_sync();
-
-    // ---- Hann along kx, power spectrum, stage A: Q(kx, ky) = sum_kz P w_z^kz.
-    // Planes -1 and 9 are the conjugate mirrors of planes 1 and 7:
-    // S(-1, ky, kz) = conj S(1, -ky, -kz), S(9, ky, kz) = conj S(7, -ky, -kz).
-    float2 QA, QB, Q8 = f2(0.f, 0.f);
-    {
-      auto hxq = [&](const float2* Hc, int kx) -> float2 {
-        float P[MZ];
-#pragma unroll
-        for (int k = 0; k < MZ; k += 2) {
-          float4 l, rr, cc;
-          if (kx == 0) {
-            const float2 m0 = s_b[sb_idx(1, (MY - ky) & 15, (MZ - k) & 7)];
-            const float2 m1 = s_b[sb_idx(1, (MY - ky) & 15, (MZ - k - 1) & 7)];
-            l = make_float4(m0.x, -m0.y, m1.x, -m1.y);
-          } else {
-            l = *reinterpret_cast<const float4*>(&s_b[sb_idx(kx - 1, ky, k)]);
-          }
-          if (kx == 8) {
-            const float2 m0 = s_b[sb_idx(7, (MY - ky) & 15, (MZ - k) & 7)];
-            const float2 m1 = s_b[sb_idx(7, (MY - ky) & 15, (MZ - k - 1) & 7)];
-            rr = make_float4(m0.x, -m0.y, m1.x, -m1.y);
-          } else {
-            rr = *reinterpret_cast<const float4*>(&s_b[sb_idx(kx + 1, ky, k)]);
-          }
-          if (Hc) cc = make_float4(Hc[k].x, Hc[k].y, Hc[k + 1].x, Hc[k + 1].y);
-          else cc = *reinterpret_cast<const float4*>(&s_b[sb_idx(kx, ky, k)]);
-          const float h0x = 2.f * cc.x - l.x - rr.x, h0y = 2.f * cc.y - l.y - rr.y;
-          const float h1x = 2.f * cc.z - l.z - rr.z, h1y = 2.f * cc.w - l.w - rr.w;
-          P[k] = h0x * h0x + h0y * h0y;
-          P[k + 1] = h1x * h1x + h1y * h1y;
-        }
-        return stageA(P);
-      };
-      if (r == 0) {
-        QA = hxq(HA, 0);
-        Q8 = hxq(nullptr, 8);
-      } else {
-        QA = hxq(HA, pA);
-      }
-      QB = hxq(HB, pB);
-    }
-    // even/odd split in ky for stage B: slot 0 = Q(0), slots 1..7 = Q(k)+Q(-k),
-    // slot 8 = Q(8), slots 9..15 = Q(16-j) - Q(j-16)... stored by the lane of
-    // ky = j as Q(-ky') - Q(ky') with ky' = 16 - j
-    const float2 mA = row_neg(QA), mB = row_neg(QB), m8 = row_neg(Q8);
-    wave_lds_sync();                     // Hann-x reads of s_b are done (s_q aliases it)
-    {
-      auto put = [&](int kx, float2 q, float2 m) {
-        float2 v;
-        if (ky == 0 || ky == 8) v = q;
-        else if (ky < 8) v = f2(q.x + m.x, q.y + m.y);
-        else v = f2(m.x - q.x, m.y - q.y);
-        s_q[kx * MY + ky] = v;
-      };
-      put(pA, QA, mA);
-      put(pB, QB, mB);
-      if (r == 0) put(8, Q8, m8);
-    }
-    wave_lds_sync();
-
-    // ---- stage B: T(kx, l_y) = Q0 + Q8 cos(pi l) + sum_k A_k cos + j B_k sin
-    if (actB) {
-      float cB[7], sB[7], c8B;
-      {
-        const float* tb = reinterpret_cast<const float*>(s_tab) + iyB * 16;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) { cB[k] = tb[k]; sB[k] = tb[7 + k]; }
-        c8B = tb[14];
-      }
-#pragma unroll 1
-      for (int j = 0; j < 3; ++j) {
-        const int kx = 3 * gB + j;
-        const float2* q = s_q + kx * MY;
-        float tx = q[0].x + c8B * q[8].x, ty = q[0].y + c8B * q[8].y;
-#pragma unroll
-        for (int k = 1; k < 8; ++k) {
-          const float2 A = q[k], Bv = q[16 - k];
-          tx += cB[k - 1] * A.x - sB[k - 1] * Bv.y;
-          ty += cB[k - 1] * A.y + sB[k - 1] * Bv.x;
-        }
-        s_t[kx * NV1_MAX + iyB] = f2(tx, ty);
-      }
-    }
-    wave_lds_sync();
-
-    // ---- stage C: R = T0 + T8 cos(pi l_x) + sum_kx 2 Re[T e^{+j phi}],
-    // smoothing and argmax
-    float bv = -INFINITY;
-    int bi = 0x7fffffff;
-    if (actC) {
-      float cC[7], sC[7], c8C;
-      {
-        const float* tc = reinterpret_cast<const float*>(s_tab) + (4 * NV1_MAX + 4 * ixC) * 4;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) { cC[k] = tc[k]; sC[k] = tc[7 + k]; }
-        c8C = tc[14];
-      }
-      for (int iy = hC; iy < nvy; iy += 3) {
-        float rv = s_t[0 * NV1_MAX + iy].x + c8C * s_t[8 * NV1_MAX + iy].x;
-#pragma unroll
-        for (int kx = 1; kx < 8; ++kx) {
-          const float2 t = s_t[kx * NV1_MAX + iy];
-          rv += cC[kx - 1] * t.x - sC[kx - 1] * t.y;
-        }
-        const int w = iy * nvx + ixC;
-        float* rp = a.rsm + pix * nv + w;
-        const float sm = (1.f - a.alpha) * rv + a.alpha * (*rp);
-        *rp = sm;
-        amax_merge(bv, bi, sm, w);
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float v2 = __shfl_xor(bv, off, 64);
-      const int i2 = __shfl_xor(bi, off, 64);
-      amax_merge(bv, bi, v2, i2);
-    }
-    const int istar = (bi < nv) ? bi : 0;
-
-    // ---- background estimate with the chosen velocity's coefficients
-    const int hsel = (a.vmode == 2) ? nv : istar;
-    float acc = 0.f;
-    {
-      const int kyc = (ky <= 8) ? ky : ky - 16;
-      if (kyc >= -a.by && kyc <= a.by) {
-        const size_t row = (size_t)hsel * (a.bx + 1);
-        if (pA <= a.bx) {
-          const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
-#pragma unroll
-          for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
-        }
-        if (pB <= a.bx) {
-          const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
-#pragma unroll
-          for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
-        }
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) {
-      const int xs = x - a.dx, ys = y - a.dy;
-      const float idel = (a.ring_delayed != nullptr && xs >= 0 && ys >= 0) ? a.ring_delayed[(size_t)ys * a.W + xs] : 0.f;
-      a.out[pix] = idel - acc;
-      if (a.vmode == 2) {
-        a.vxy[pix] = make_float2(a.fvx, a.fvy);
-        a.vidx[pix] = -1;
-      } else {
-        a.vxy[pix] = make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
-        a.vidx[pix] = istar;
-      }
-    }
-  }
+  pixel16_tile(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
 }
 
 }  // namespace p16
