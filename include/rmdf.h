@@ -71,6 +71,8 @@ typedef struct {
   int kernel_variant;       /* per-pixel kernel: 0 auto, 1 generic (LDS-staged,
                                any compiled shape), 2 one wavefront per anchor
                                (16x16x8, at most 21 candidates per axis)       */
+  int write_features;       /* search mode that also writes the learned model's
+                               input features each frame (rmdf_features)       */
 } rmdf_params;
 
 /* Fill *p with the defaults above (the -1 / negative markers). */
@@ -125,11 +127,58 @@ rmdf_status rmdf_spectrum(rmdf_ctx *ctx, int npix, const int *xs, const int *ys,
 rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);
 
 /* Per-kernel timing with HIP events on the context stream (off by default).
- * which: 0 = pixel kernel, 1 = row sliding-DFT kernel, 2 = ingest.
+ * which: 0 = pixel kernel, 1 = row sliding-DFT kernel, 2 = ingest,
+ * 3 = learned-model network (three kernels), 4 = learned-mode finish kernel.
  * Returns the summed milliseconds and the number of timed launches since the
  * last reset (reading synchronises the stream). */
 rmdf_status rmdf_set_timing(rmdf_ctx *ctx, int on);
 rmdf_status rmdf_kernel_time(rmdf_ctx *ctx, int which, double *ms, long long *launches);
+
+/* ---- Learned velocity surrogate (16x16x8 window) ----------------------
+ * Not in the paper: a small network maps each anchor's local power spectrum
+ * (the P of eq. 9) to (vx, vy, confidence); where the confidence is below
+ * conf_threshold the anchor falls back to the search over the grid (eq. 10
+ * without the smoother, which this mode does not keep).  Input features:
+ * x = ln(P + 1e-6 max P) minus its mean over all Mx*My*Mz bins, stored for
+ * kx = 0..8 as [kx][ky][kz] (1152 BF16 per anchor; P is even, so the other
+ * half repeats them and the first layer is kept folded over +-k).
+ * Layers: 1152 -> 128 (ReLU) -> 64 (ReLU) -> 3, BF16 weights on MFMA with
+ * FP32 accumulation for the first two, FP32 for the last.
+ * Weight blob (host, FP32, row-major [out][in]): W1 128x1152, b1 128,
+ * W2 64x128, b2 64, W3 3x64, b3 3 (bytes = 4 * 155,907).  The velocity index
+ * of an anchor that used the network is -2. */
+rmdf_status rmdf_mlp_set_weights(rmdf_ctx *ctx, const float *blob, size_t bytes);
+/* Features of the latest frame, feat_dev[H*W][1152] BF16 (learned mode or
+ * write_features).  Errors: RMDF_E_STATE. */
+rmdf_status rmdf_features(rmdf_ctx *ctx, void *feat_dev);
+/* Network output of the latest frame, vc_dev[H*W][3] = (vx, vy, confidence). */
+rmdf_status rmdf_learned_output(rmdf_ctx *ctx, float *vc_dev);
+
+/* Kernels of the learned model, for training (all asynchronous on `stream`,
+ * device pointers; BF16 as uint16).  rmdf_mlp_gemm_nt:
+ * C[M][N] = epi(A[M][K] . B[N][K]^T + bias[N]) with A, B BF16 row-major
+ * (K contiguous, K, lda, ldb multiples of 8); epi 0 none, 1 ReLU, 2 multiply
+ * by (aux[m][n] > 0) (ReLU gradient, aux BF16); output FP32 (Cf) and/or BF16
+ * (Cb) with leading dimension ldc.  Errors: RMDF_E_INVAL, RMDF_E_DEVICE. */
+rmdf_status rmdf_mlp_gemm_nt(const void *A, int lda, const void *B, int ldb, int M, int N, int K, const float *bias,
+                             int epi, const void *aux, int ldaux, float *Cf, void *Cb, int ldc, void *stream);
+/* out[c][r] = in[r][c]; input BF16 (in_bf16) or FP32 (in_f32, rounded). */
+rmdf_status rmdf_mlp_transpose(const void *in_bf16, const float *in_f32, int R, int C, void *out_bf16, void *stream);
+/* Last layer, loss and its gradient for n samples: o = W3 h2 + b3;
+ * loss = sum_b [wv ((o0-lx)^2 + (o1-ly)^2) + BCE(o2, t)] / n with
+ * t = [max(|o0-lx|, |o1-ly|) <= half_step]; writes dh2 (BF16, masked by
+ * h2 > 0); adds into dW3 (3x64), db3 (3) and *loss. */
+rmdf_status rmdf_mlp_head(const void *h2, const float *W3, const float *b3, const float *labels, int n, float wv,
+                          float half_step, void *dh2, float *dW3, float *db3, float *loss, void *stream);
+/* out[j] = sum_r in[r][j], in BF16 R x C (bias gradients). */
+rmdf_status rmdf_mlp_colsum(const void *in, int R, int C, float *out, void *stream);
+/* Inference head: vxyc[b] = (o0, o1, sigmoid(o2)). */
+rmdf_status rmdf_mlp_infer_head(const void *h2, const float *W3, const float *b3, int n, float *vxyc, void *stream);
+/* Adam step (FP32 master weights p, gradient g, moments m, v); writes the
+ * BF16 copy p_bf16 when non-NULL.  step counts from 1. */
+rmdf_status rmdf_mlp_adam(float *p, const float *g, float *m, float *v, void *p_bf16, int n, float lr, float b1,
+                          float b2, float eps, int step, void *stream);
+rmdf_status rmdf_mlp_to_bf16(const float *in, void *out_bf16, long long n, void *stream);
 
 /* Per-pixel kernel variant the context launches (1 generic, 2 one wavefront
  * per anchor), after resolving kernel_variant = 0. */

@@ -37,7 +37,7 @@ class rmdf_params(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("velocity_mode", ctypes.c_int),
                 ("fixed_vx", ctypes.c_float), ("fixed_vy", ctypes.c_float),
                 ("conf_threshold", ctypes.c_float), ("tile_rows", ctypes.c_int),
-                ("kernel_variant", ctypes.c_int)]
+                ("kernel_variant", ctypes.c_int), ("write_features", ctypes.c_int)]
 
 
 # C signatures: name -> (restype, argtypes)
@@ -59,6 +59,17 @@ _SIGS = {
     "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
+    "rmdf_mlp_set_weights": (_I, [_VP, _VP, _SZ]),
+    "rmdf_features": (_I, [_VP, _VP]),
+    "rmdf_learned_output": (_I, [_VP, _VP]),
+    "rmdf_mlp_gemm_nt": (_I, [_VP, _I, _VP, _I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _VP, _I, _VP]),
+    "rmdf_mlp_transpose": (_I, [_VP, _VP, _I, _I, _VP, _VP]),
+    "rmdf_mlp_head": (_I, [_VP, _VP, _VP, _VP, _I, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP, _VP, _VP]),
+    "rmdf_mlp_colsum": (_I, [_VP, _I, _I, _VP, _VP]),
+    "rmdf_mlp_infer_head": (_I, [_VP, _VP, _VP, _I, _VP, _VP]),
+    "rmdf_mlp_adam": (_I, [_VP, _VP, _VP, _VP, _VP, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                           ctypes.c_float, _I, _VP]),
+    "rmdf_mlp_to_bf16": (_I, [_VP, _VP, ctypes.c_longlong, _VP]),
     "rmdf_batch_create": (_I, [_I, _VP, ctypes.POINTER(rmdf_params), _VP, ctypes.POINTER(_VP)]),
     "rmdf_batch_input": (_I, [_VP, _I, ctypes.POINTER(_VP)]),
     "rmdf_batch_launch": (_I, [_VP]),
@@ -173,7 +184,7 @@ class Filter:
 
     def __init__(self, H, W, Kx, Ky, Kt, vgrid_x, vgrid_y, *, Bx=-1, By=-1, delay=(-1, -1, -1),
                  alpha=-1.0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0), conf_threshold=0.9,
-                 tile_rows=0, kernel_variant=0, stream=None, use_torch_stream=True):
+                 tile_rows=0, kernel_variant=0, write_features=False, stream=None, use_torch_stream=True):
         import torch
         p = rmdf_params_default()
         p.Bx, p.By = int(Bx), int(By)
@@ -184,6 +195,7 @@ class Filter:
         p.conf_threshold = float(conf_threshold)
         p.tile_rows = int(tile_rows)
         p.kernel_variant = int(kernel_variant)
+        p.write_features = int(bool(write_features))
         if stream is None and use_torch_stream:
             stream = torch.cuda.current_stream().cuda_stream
         self.H, self.W, self.M = int(H), int(W), (int(Kx), int(Ky), int(Kt))
@@ -237,6 +249,26 @@ class Filter:
         ms, n = ctypes.c_double(), ctypes.c_longlong()
         _check(lib().rmdf_kernel_time(self.ctx, int(which), ctypes.byref(ms), ctypes.byref(n)), self.ctx)
         return ms.value, n.value
+
+    def set_weights(self, blob):
+        """Learned-mode weights: FP32 array W1 (128x1152), b1, W2 (64x128), b2,
+        W3 (3x64), b3 (see rmdf_mlp_set_weights)."""
+        w = np.ascontiguousarray(blob, np.float32)
+        _check(lib().rmdf_mlp_set_weights(self.ctx, w.ctypes.data, w.nbytes), self.ctx)
+
+    def features(self):
+        """Learned-model input features of the latest frame, [H, W, 1152] BF16
+        (returned as a torch.bfloat16 tensor)."""
+        import torch
+        out = torch.empty((self.H, self.W, 1152), dtype=torch.bfloat16, device="cuda")
+        _check(lib().rmdf_features(self.ctx, out.data_ptr()), self.ctx)
+        return out
+
+    def learned_output(self):
+        import torch
+        out = torch.empty((self.H, self.W, 3), dtype=torch.float32, device="cuda")
+        _check(lib().rmdf_learned_output(self.ctx, out.data_ptr()), self.ctx)
+        return out
 
     def kernel_name(self) -> str:
         """Name of the per-pixel kernel this context launches."""
@@ -367,3 +399,59 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---- learned-model kernels on torch tensors (argument marshalling only) ----
+
+def _stream_handle():
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _p(t):
+    return None if t is None else t.data_ptr()
+
+
+def mlp_gemm_nt(A, B, bias=None, epi=0, aux=None, out_f32=None, out_bf16=None):
+    """C = epi(A @ B.T + bias); A [M, K], B [N, K] torch.bfloat16 contiguous."""
+    M, K = A.shape
+    N = B.shape[0]
+    ldc = (out_f32 if out_f32 is not None else out_bf16).shape[1]
+    _check(lib().rmdf_mlp_gemm_nt(A.data_ptr(), A.shape[1], B.data_ptr(), B.shape[1], M, N, K, _p(bias), int(epi),
+                                  _p(aux), 0 if aux is None else aux.shape[1], _p(out_f32), _p(out_bf16), ldc,
+                                  ctypes.c_void_p(_stream_handle())))
+
+
+def mlp_transpose(inp, out):
+    import torch
+    R, C = inp.shape
+    if inp.dtype == torch.bfloat16:
+        _check(lib().rmdf_mlp_transpose(inp.data_ptr(), None, R, C, out.data_ptr(), ctypes.c_void_p(_stream_handle())))
+    else:
+        _check(lib().rmdf_mlp_transpose(None, inp.data_ptr(), R, C, out.data_ptr(), ctypes.c_void_p(_stream_handle())))
+
+
+def mlp_head(h2, W3, b3, labels, wv, half_step, dh2, dW3, db3, loss):
+    _check(lib().rmdf_mlp_head(h2.data_ptr(), W3.data_ptr(), b3.data_ptr(), labels.data_ptr(), h2.shape[0],
+                               float(wv), float(half_step), dh2.data_ptr(), dW3.data_ptr(), db3.data_ptr(),
+                               loss.data_ptr(), ctypes.c_void_p(_stream_handle())))
+
+
+def mlp_colsum(inp, out):
+    R, C = inp.shape
+    _check(lib().rmdf_mlp_colsum(inp.data_ptr(), R, C, out.data_ptr(), ctypes.c_void_p(_stream_handle())))
+
+
+def mlp_infer_head(h2, W3, b3, out):
+    _check(lib().rmdf_mlp_infer_head(h2.data_ptr(), W3.data_ptr(), b3.data_ptr(), h2.shape[0], out.data_ptr(),
+                                     ctypes.c_void_p(_stream_handle())))
+
+
+def mlp_adam(p, g, m, v, p_bf16, lr, step, b1=0.9, b2=0.999, eps=1e-8):
+    _check(lib().rmdf_mlp_adam(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), _p(p_bf16), p.numel(),
+                               float(lr), float(b1), float(b2), float(eps), int(step),
+                               ctypes.c_void_p(_stream_handle())))
+
+
+def mlp_to_bf16(inp, out):
+    _check(lib().rmdf_mlp_to_bf16(inp.data_ptr(), out.data_ptr(), inp.numel(), ctypes.c_void_p(_stream_handle())))

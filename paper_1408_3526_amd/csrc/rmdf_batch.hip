@@ -90,7 +90,7 @@ k_batch_persistent(const BatchPixDesc* __restrict__ d, const int4* __restrict__ 
       case KIND_884: pixel_tile<8, 8, 4>(bd.a, rd, w.y, w.z, smem); break;
       case KIND_995: pixel_tile<9, 9, 5>(bd.a, rd, w.y, w.z, smem); break;
       case KIND_16G: pixel_tile<16, 16, 8>(bd.a, rd, w.y, w.z, smem); break;
-      default: p16::pixel16_tile(bd.a, rd, w.y, w.z, smem); break;
+      default: p16::pixel16_tile<0>(bd.a, rd, w.y, w.z, smem); break;
     }
   }
   // the last workgroup out advances the frame counters and re-arms the queue

@@ -49,6 +49,15 @@ struct rmdf_ctx {
   float2 *tauy = nullptr, *taux = nullptr, *htab = nullptr;
   float *gx = nullptr, *gy = nullptr, *tabB = nullptr, *tabC = nullptr;
   int variant = 0;                 // resolved kernel variant (1 generic, 2 wave-per-anchor)
+  int write_features = 0;          // plain search that also writes the learned-model input
+  // learned velocity surrogate (16x16x8): features, hidden activations, outputs, weights
+  unsigned short* feat = nullptr;  // [HW][1152] BF16
+  int* fidx = nullptr;             // [HW] search index (fallback)
+  unsigned short *h1 = nullptr, *h2 = nullptr;   // [HW][128], [HW][64] BF16
+  float* vc = nullptr;             // [HW][3] network output (vx, vy, confidence)
+  unsigned short *w1 = nullptr, *w2 = nullptr;   // BF16 [128][1152], [64][128]
+  float *b1 = nullptr, *b2 = nullptr, *w3 = nullptr, *b3 = nullptr;
+  bool weights_set = false;
   unsigned long long* nonfinite = nullptr;
   int* xy_scratch = nullptr;
   int xy_cap = 0;
@@ -57,8 +66,8 @@ struct rmdf_ctx {
   // timing
   bool timing = false;
   std::vector<EventPair> events;
-  double ms[3] = {0, 0, 0};
-  long long launches[3] = {0, 0, 0};
+  double ms[5] = {0, 0, 0, 0, 0};
+  long long launches[5] = {0, 0, 0, 0, 0};
   std::string err;
 };
 
@@ -222,6 +231,7 @@ rmdf::PixArgs rmdf_internal_pixargs(const rmdf_ctx* c) {
   a.out = c->out; a.vxy = c->vxy; a.vidx = c->vidx;
   a.twy = c->twy; a.twz = c->twz; a.twA = c->twA; a.tauy = c->tauy; a.taux = c->taux; a.htab = c->htab;
   a.gx = c->gx; a.gy = c->gy; a.tabB = c->tabB; a.tabC = c->tabC;
+  a.feat = c->feat; a.fidx = c->fidx; a.dt = c->dt;
   return a;
 }
 const float* rmdf_internal_ring(const rmdf_ctx* c, int* nring, int* dt) {
@@ -249,6 +259,7 @@ void rmdf_params_default(rmdf_params* p) {
   p->conf_threshold = 0.9f;
   p->tile_rows = 0;
   p->kernel_variant = 0;
+  p->write_features = 0;
 }
 
 rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid_x, int nvx, const float* vgrid_y,
@@ -278,8 +289,8 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   if (dx >= Kx || dy >= Ky || dt >= Kt) return fail(nullptr, RMDF_E_INVAL, "delay m' must be < M");
   const float alpha = p.alpha < 0.f ? std::exp(-0.1f) : p.alpha;
   if (!(alpha >= 0.f && alpha < 1.f)) return fail(nullptr, RMDF_E_INVAL, "alpha must be in [0, 1)");
-  if (p.velocity_mode != RMDF_VEL_SEARCH && p.velocity_mode != RMDF_VEL_FIXED)
-    return fail(nullptr, RMDF_E_UNSUPPORTED, "velocity mode not available in this context type");
+  if (p.velocity_mode < RMDF_VEL_SEARCH || p.velocity_mode > RMDF_VEL_FIXED)
+    return fail(nullptr, RMDF_E_INVAL, "unknown velocity mode");
   if (p.velocity_mode == RMDF_VEL_FIXED && !(std::isfinite(p.fixed_vx) && std::isfinite(p.fixed_vy)))
     return fail(nullptr, RMDF_E_INVAL, "fixed velocity must be finite");
   if (p.tile_rows < 0) return fail(nullptr, RMDF_E_INVAL, "tile_rows must be >= 0");
@@ -287,6 +298,10 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   const bool w16 = rmdf::pixel16_eligible(Kx, Ky, Kt, nvx, nvy);
   if (p.kernel_variant == 2 && !w16)
     return fail(nullptr, RMDF_E_UNSUPPORTED, "kernel_variant 2 needs a 16x16x8 window and at most 21 candidates per axis");
+  const bool needs16 = (p.velocity_mode == RMDF_VEL_LEARNED) || p.write_features;
+  if (needs16 && (!w16 || p.kernel_variant == 1))
+    return fail(nullptr, RMDF_E_UNSUPPORTED,
+                "the learned velocity model and its features need the 16x16x8 window, kernel variant 2 and at most 21 candidates per axis");
   if (!rmdf::shape_supported(Kx, Ky, Kt))
     return fail(nullptr, RMDF_E_UNSUPPORTED, "window shape has no compiled kernel (8x8x4, 16x16x8, 9x9x5)");
 
@@ -306,6 +321,7 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   c->conf = p.conf_threshold;
   c->TY = p.tile_rows > 0 ? p.tile_rows : 32;
   c->variant = p.kernel_variant != 0 ? p.kernel_variant : (w16 ? 2 : 1);
+  c->write_features = p.write_features ? 1 : 0;
   c->nring = dt + 1;
   // NULL: the device's default (null) stream, which is also torch's default
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -328,6 +344,19 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   if ((e = dalloc(c, &c->vidx, HW)) != hipSuccess) return bail(e, "velocity index");
   if ((e = dalloc(c, &c->nonfinite, 1)) != hipSuccess) return bail(e, "counter");
   if ((e = build_tables(c, vgrid_x, vgrid_y)) != hipSuccess) return bail(e, "tables");
+  if (needs16 && (e = dalloc(c, &c->feat, HW * 1152)) != hipSuccess) return bail(e, "features");
+  if (c->vmode == RMDF_VEL_LEARNED) {
+    if ((e = dalloc(c, &c->fidx, HW)) != hipSuccess) return bail(e, "fallback index");
+    if ((e = dalloc(c, &c->h1, HW * 128)) != hipSuccess) return bail(e, "hidden layer");
+    if ((e = dalloc(c, &c->h2, HW * 64)) != hipSuccess) return bail(e, "hidden layer");
+    if ((e = dalloc(c, &c->vc, HW * 3)) != hipSuccess) return bail(e, "network output");
+    if ((e = dalloc(c, &c->w1, (size_t)128 * 1152)) != hipSuccess) return bail(e, "weights");
+    if ((e = dalloc(c, &c->w2, (size_t)64 * 128)) != hipSuccess) return bail(e, "weights");
+    if ((e = dalloc(c, &c->b1, 128)) != hipSuccess) return bail(e, "weights");
+    if ((e = dalloc(c, &c->b2, 64)) != hipSuccess) return bail(e, "weights");
+    if ((e = dalloc(c, &c->w3, 192)) != hipSuccess) return bail(e, "weights");
+    if ((e = dalloc(c, &c->b3, 3)) != hipSuccess) return bail(e, "weights");
+  }
   // zero the state (observer, smoother, ring) on the context stream
   if ((e = hipMemsetAsync(c->st, 0, HW * c->NCOL * Kt * sizeof(float2), c->stream)) != hipSuccess) return bail(e, "memset");
   if ((e = hipMemsetAsync(c->rsm, 0, HW * c->nv * sizeof(float), c->stream)) != hipSuccess) return bail(e, "memset");
@@ -369,10 +398,30 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
 
   rmdf::PixArgs a = rmdf_internal_pixargs(c);
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
+  if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
+  const int mode = (c->vmode == RMDF_VEL_LEARNED) ? 2 : (c->write_features ? 1 : 0);
   timed_begin(c, 0, &ev);
-  e = (c->variant == 2) ? rmdf::launch_pixel16(a, c->stream) : rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
+  e = (c->variant == 2) ? rmdf::launch_pixel16(a, mode, c->stream)
+                        : rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
   timed_end(c, &ev);
   if (e != hipSuccess) return hip_fail(c, e, "pixel kernel launch");
+  if (mode == 2) {
+    // network on every anchor's features (BF16 MFMA, FP32 accumulate), then
+    // the background estimate with the chosen velocity
+    const int n = c->H * c->W;
+    timed_begin(c, 3, &ev);
+    rmdf_status st = rmdf_mlp_gemm_nt(c->feat, 1152, c->w1, 1152, n, 128, 1152, c->b1, 1, nullptr, 0, nullptr, c->h1,
+                                      128, c->stream);
+    if (st == RMDF_OK)
+      st = rmdf_mlp_gemm_nt(c->h1, 128, c->w2, 128, n, 64, 128, c->b2, 1, nullptr, 0, nullptr, c->h2, 64, c->stream);
+    if (st == RMDF_OK) st = rmdf_mlp_infer_head(c->h2, c->w3, c->b3, n, c->vc, c->stream);
+    timed_end(c, &ev);
+    if (st != RMDF_OK) return fail(c, st, "network launch failed");
+    timed_begin(c, 4, &ev);
+    e = rmdf::launch_finish16(a, c->vc, c->conf, c->stream);
+    timed_end(c, &ev);
+    if (e != hipSuccess) return hip_fail(c, e, "finish kernel launch");
+  }
   c->t += 1;
   return RMDF_OK;
 }
@@ -457,7 +506,7 @@ rmdf_status rmdf_set_timing(rmdf_ctx* c, int on) {
 }
 
 rmdf_status rmdf_kernel_time(rmdf_ctx* c, int which, double* ms, long long* launches) {
-  if (!c || which < 0 || which > 2 || !ms || !launches) return fail(c, RMDF_E_INVAL, "bad arguments");
+  if (!c || which < 0 || which > 4 || !ms || !launches) return fail(c, RMDF_E_INVAL, "bad arguments");
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "sync");
   for (auto& ev : c->events) {
@@ -473,6 +522,58 @@ rmdf_status rmdf_kernel_time(rmdf_ctx* c, int which, double* ms, long long* laun
   *launches = c->launches[which];
   c->ms[which] = 0;
   c->launches[which] = 0;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_mlp_set_weights(rmdf_ctx* c, const float* w, size_t bytes) {
+  if (!c || !w) return fail(c, RMDF_E_INVAL, "NULL argument");
+  if (c->vmode != RMDF_VEL_LEARNED) return fail(c, RMDF_E_STATE, "context is not in learned mode");
+  const size_t n1 = 128 * 1152, n2 = 64 * 128;
+  const size_t total = n1 + 128 + n2 + 64 + 192 + 3;
+  if (bytes != total * sizeof(float)) return fail(c, RMDF_E_INVAL, "weight blob has the wrong size");
+  for (size_t i = 0; i < total; ++i)
+    if (!std::isfinite(w[i])) return fail(c, RMDF_E_INVAL, "non-finite weight");
+  auto bf = [](float f) {
+    unsigned int u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+  };
+  std::vector<unsigned short> w1(n1), w2(n2);
+  for (size_t i = 0; i < n1; ++i) w1[i] = bf(w[i]);
+  const float* p = w + n1;
+  const float* b1 = p; p += 128;
+  for (size_t i = 0; i < n2; ++i) w2[i] = bf(p[i]);
+  p += n2;
+  const float* b2 = p; p += 64;
+  const float* w3 = p; p += 192;
+  const float* b3 = p;
+  hipError_t e;
+  if ((e = hipMemcpy(c->w1, w1.data(), n1 * 2, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  if ((e = hipMemcpy(c->w2, w2.data(), n2 * 2, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  if ((e = hipMemcpy(c->b1, b1, 128 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  if ((e = hipMemcpy(c->b2, b2, 64 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  if ((e = hipMemcpy(c->w3, w3, 192 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  if ((e = hipMemcpy(c->b3, b3, 3 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  c->weights_set = true;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_features(rmdf_ctx* c, void* feat_dev) {
+  if (!c || !feat_dev) return fail(c, RMDF_E_INVAL, "NULL argument");
+  if (!c->feat) return fail(c, RMDF_E_STATE, "context computes no features");
+  if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
+  hipError_t e = hipMemcpyAsync(feat_dev, c->feat, (size_t)c->H * c->W * 1152 * 2, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_learned_output(rmdf_ctx* c, float* vc_dev) {
+  if (!c || !vc_dev) return fail(c, RMDF_E_INVAL, "NULL argument");
+  if (!c->vc) return fail(c, RMDF_E_STATE, "context is not in learned mode");
+  if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
+  hipError_t e = hipMemcpyAsync(vc_dev, c->vc, (size_t)c->H * c->W * 3 * 4, hipMemcpyDeviceToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy");
   return RMDF_OK;
 }
 

@@ -35,6 +35,9 @@ struct PixArgs {
   const float* gy;             // [nvy]
   const float* tabB;           // [nvy][16] cos/sin(2 pi k l_y / 16), k = 1..7; cos(pi l_y)
   const float* tabC;           // [nvx][16] 2cos/2sin(2 pi k l_x / 16), k = 1..7; cos(pi l_x)
+  unsigned short* feat;        // [H][W][9][16][8] BF16 learned-model features (16x16x8), or nullptr
+  int* fidx;                   // [H][W] search index for the learned-mode fallback
+  int dt;                      // temporal output delay
 };
 
 bool shape_supported(int mx, int my, int mz);
@@ -44,7 +47,8 @@ hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
                            hipStream_t s);
 bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
-hipError_t launch_pixel16(const PixArgs& a, hipStream_t s);
+hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
+hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, hipStream_t s);
 hipError_t launch_ingest(const float* in, float* slot, long long n, unsigned long long* nonfinite, hipStream_t s);
 
 }  // namespace rmdf

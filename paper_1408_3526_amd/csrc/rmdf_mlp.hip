@@ -1,0 +1,292 @@
+// rmdf_mlp.hip - kernels of the learned velocity surrogate: a small MLP
+// (input: the log power spectrum of a pixel's local window; hidden 128 and 64
+// with ReLU; output vx, vy and a confidence logit) trained and evaluated with
+// BF16 operands on MFMA and FP32 accumulation.
+//
+//   k_gemm_nt     C[M][N] = act(A[M][K] . B[N][K]^T + bias)   (v_mfma 32x32x16 bf16)
+//   k_transpose   BF16 / FP32 -> BF16 transpose (operands of the weight-gradient GEMMs)
+//   k_head        layer 3 (64 -> 3), loss and its gradient, dH2, dW3/db3 partial sums
+//   k_infer_head  layer 3 for inference, confidence = sigmoid(logit)
+//   k_adam        Adam update of FP32 master weights + BF16 copy
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+
+#include "../../include/rmdf.h"
+
+namespace rmdf {
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LDSK = BK + 8;   // bf16 per LDS row (80 B): rows 16-byte aligned, banks spread
+
+enum : int { EPI_NONE = 0, EPI_RELU = 1, EPI_RELU_GRAD = 2 };
+
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  // round to nearest even
+  unsigned int u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as_float(((unsigned int)b) << 16); }
+
+// C = epi(A . B^T + bias).  A: M x K (lda), B: N x K (ldb), BF16 row-major,
+// K contiguous.  Output FP32 (Cf) and/or BF16 (Cb), row-major ldc.
+// EPI_RELU_GRAD multiplies by (aux[m][n] > 0) where aux is BF16 (ldaux).
+__global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restrict__ A, int lda,
+                                                 const unsigned short* __restrict__ B, int ldb, int M, int N, int K,
+                                                 const float* __restrict__ bias, int epi,
+                                                 const unsigned short* __restrict__ aux, int ldaux,
+                                                 float* __restrict__ Cf, unsigned short* __restrict__ Cb, int ldc) {
+  __shared__ __align__(16) unsigned short sA[BM * LDSK];
+  __shared__ __align__(16) unsigned short sB[BN * LDSK];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = wv >> 1, wn = wv & 1;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
+  // loader: thread -> (row = tid / 4, 8 bf16 at k = (tid % 4) * 8)
+  const int lr = tid >> 2, lk = (tid & 3) * 8;
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+    const int gk = k0 + lk;
+    if (m0 + lr < M && gk < K) va = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + lr) * lda + gk);
+    if (n0 + lr < N && gk < K) vb = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + lr) * ldb + gk);
+    __syncthreads();
+    *reinterpret_cast<uint4*>(&sA[lr * LDSK + lk]) = va;
+    *reinterpret_cast<uint4*>(&sB[lr * LDSK + lk]) = vb;
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 16) {
+      const int r = lane & 31, kq = kk + (lane >> 5) * 8;
+      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[(wm * 32 + r) * LDSK + kq]);
+      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[(wn * 32 + r) * LDSK + kq]);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+  }
+  // D layout: column = lane % 32; row = (i / 4) * 8 + (lane / 32) * 4 + i % 4
+  const int col = n0 + wn * 32 + (lane & 31);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int row = m0 + wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+    if (row < M && col < N) {
+      float v = acc[i] + (bias ? bias[col] : 0.f);
+      if (epi == EPI_RELU) v = v > 0.f ? v : 0.f;
+      else if (epi == EPI_RELU_GRAD) v = (bf16_float(aux[(size_t)row * ldaux + col]) > 0.f) ? v : 0.f;
+      if (Cf) Cf[(size_t)row * ldc + col] = v;
+      if (Cb) Cb[(size_t)row * ldc + col] = bf16_bits(v);
+    }
+  }
+}
+
+// out[c][r] = in[r][c] (in: R x C, FP32 when inf != nullptr else BF16)
+__global__ void __launch_bounds__(256) k_transpose(const unsigned short* __restrict__ inb, const float* __restrict__ inf,
+                                                   int R, int C, unsigned short* __restrict__ out) {
+  __shared__ unsigned short tile[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int j = ty; j < 32; j += 8) {
+    const int r = by + j, c = bx + tx;
+    unsigned short v = 0;
+    if (r < R && c < C) v = inf ? bf16_bits(inf[(size_t)r * C + c]) : inb[(size_t)r * C + c];
+    tile[j][tx] = v;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int c = bx + j, r = by + tx;
+    if (c < C && r < R) out[(size_t)c * R + r] = tile[tx][j];
+  }
+}
+
+// Layer 3 + loss + gradient for a batch of n samples.
+//   o = W3 h2 + b3 (W3: 3 x 64, FP32), loss = wv * ((o0-lx)^2 + (o1-ly)^2) / n
+//        + BCE(o2, t) / n,  t = [max(|o0-lx|, |o1-ly|) <= half_step]
+// Writes dH2 (BF16, masked by h2 > 0), accumulates dW3, db3 (FP32, atomics per
+// block) and the loss sum.
+__global__ void __launch_bounds__(256) k_head(const unsigned short* __restrict__ h2, const float* __restrict__ W3,
+                                              const float* __restrict__ b3, const float* __restrict__ lab, int n,
+                                              float wv, float half_step, unsigned short* __restrict__ dh2,
+                                              float* __restrict__ dW3, float* __restrict__ db3,
+                                              float* __restrict__ loss) {
+  __shared__ float sW[3 * 64 + 3];
+  for (int i = threadIdx.x; i < 3 * 64; i += 256) sW[i] = W3[i];
+  if (threadIdx.x < 3) sW[192 + threadIdx.x] = b3[threadIdx.x];
+  __syncthreads();
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  float d[3] = {0.f, 0.f, 0.f};
+  float l = 0.f;
+  float hv[64];
+  if (b < n) {
+    const unsigned short* hp = h2 + (size_t)b * 64;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) hv[j] = bf16_float(hp[j]);
+    float o[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      float s = sW[192 + q];
+#pragma unroll
+      for (int j = 0; j < 64; ++j) s += sW[q * 64 + j] * hv[j];
+      o[q] = s;
+    }
+    const float ex = o[0] - lab[2 * b], ey = o[1] - lab[2 * b + 1];
+    const float t = (fmaxf(fabsf(ex), fabsf(ey)) <= half_step) ? 1.f : 0.f;
+    const float sp = 1.f / (1.f + expf(-o[2]));
+    const float inv = 1.f / (float)n;
+    // BCE with logits, stable form: max(o,0) - o t + log(1 + exp(-|o|))
+    l = wv * (ex * ex + ey * ey) * inv + (fmaxf(o[2], 0.f) - o[2] * t + log1pf(expf(-fabsf(o[2])))) * inv;
+    d[0] = 2.f * wv * ex * inv;
+    d[1] = 2.f * wv * ey * inv;
+    d[2] = (sp - t) * inv;
+    unsigned short* dp = dh2 + (size_t)b * 64;
+#pragma unroll
+    for (int j = 0; j < 64; ++j) {
+      const float g = sW[j] * d[0] + sW[64 + j] * d[1] + sW[128 + j] * d[2];
+      dp[j] = bf16_bits(hv[j] > 0.f ? g : 0.f);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 64; ++j) hv[j] = 0.f;
+  }
+  // dW3[q][j] += sum_b d[q] hv[j]; reduce over the block through LDS
+  for (int q = 0; q < 3; ++q) {
+    for (int j = 0; j < 64; ++j) {
+      float v = d[q] * hv[j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+      if ((threadIdx.x & 63) == 0) atomicAdd(&dW3[q * 64 + j], v);
+    }
+    float v = d[q];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&db3[q], v);
+  }
+  for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, l);
+}
+
+// Column sums (bias gradients): out[j] = sum_r in[r][j] (in BF16 R x C)
+__global__ void __launch_bounds__(256) k_colsum(const unsigned short* __restrict__ in, int R, int C,
+                                                float* __restrict__ out) {
+  const int j = blockIdx.x;
+  float s = 0.f;
+  for (int r = threadIdx.x; r < R; r += 256) s += bf16_float(in[(size_t)r * C + j]);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  __shared__ float sp[4];
+  if ((threadIdx.x & 63) == 0) sp[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[j] = sp[0] + sp[1] + sp[2] + sp[3];
+}
+
+// Inference head: (vx, vy, confidence) per sample.
+__global__ void __launch_bounds__(256) k_infer_head(const unsigned short* __restrict__ h2, const float* __restrict__ W3,
+                                                    const float* __restrict__ b3, int n, float* __restrict__ vxyc) {
+  __shared__ float sW[3 * 64 + 3];
+  for (int i = threadIdx.x; i < 3 * 64; i += 256) sW[i] = W3[i];
+  if (threadIdx.x < 3) sW[192 + threadIdx.x] = b3[threadIdx.x];
+  __syncthreads();
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= n) return;
+  const unsigned short* hp = h2 + (size_t)b * 64;
+  float o[3] = {sW[192], sW[193], sW[194]};
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    const float h = bf16_float(hp[j]);
+    o[0] += sW[j] * h;
+    o[1] += sW[64 + j] * h;
+    o[2] += sW[128 + j] * h;
+  }
+  vxyc[3 * b] = o[0];
+  vxyc[3 * b + 1] = o[1];
+  vxyc[3 * b + 2] = 1.f / (1.f + expf(-o[2]));
+}
+
+// Adam on FP32 master weights; writes the BF16 copy used by the GEMMs.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                              float* __restrict__ v, unsigned short* __restrict__ pb, int n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pi;
+  if (pb) pb[i] = bf16_bits(pi);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ in, unsigned short* __restrict__ out, long long n) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = bf16_bits(in[i]);
+}
+
+}  // namespace mlp
+}  // namespace rmdf
+
+using namespace rmdf::mlp;
+
+static hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+static rmdf_status st_of(hipError_t e) { return e == hipSuccess ? RMDF_OK : RMDF_E_DEVICE; }
+
+extern "C" {
+
+rmdf_status rmdf_mlp_gemm_nt(const void* A, int lda, const void* B, int ldb, int M, int N, int K, const float* bias,
+                             int epi, const void* aux, int ldaux, float* Cf, void* Cb, int ldc, void* stream) {
+  if (!A || !B || M < 1 || N < 1 || K < 1 || (K % 8) || (lda % 8) || (ldb % 8) || (!Cf && !Cb) || epi < 0 || epi > 2 ||
+      (epi == EPI_RELU_GRAD && !aux))
+    return RMDF_E_INVAL;
+  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, S(stream), (const unsigned short*)A, lda,
+                     (const unsigned short*)B, ldb, M, N, K, bias, epi, (const unsigned short*)aux, ldaux, Cf,
+                     (unsigned short*)Cb, ldc);
+  return st_of(hipGetLastError());
+}
+
+rmdf_status rmdf_mlp_transpose(const void* in_bf16, const float* in_f32, int R, int C, void* out_bf16, void* stream) {
+  if ((!in_bf16 && !in_f32) || !out_bf16 || R < 1 || C < 1) return RMDF_E_INVAL;
+  dim3 grid((C + 31) / 32, (R + 31) / 32);
+  hipLaunchKernelGGL(k_transpose, grid, dim3(256), 0, S(stream), (const unsigned short*)in_bf16, in_f32, R, C,
+                     (unsigned short*)out_bf16);
+  return st_of(hipGetLastError());
+}
+
+rmdf_status rmdf_mlp_head(const void* h2, const float* W3, const float* b3, const float* labels, int n, float wv,
+                          float half_step, void* dh2, float* dW3, float* db3, float* loss, void* stream) {
+  if (!h2 || !W3 || !b3 || !labels || n < 1 || !dh2 || !dW3 || !db3 || !loss) return RMDF_E_INVAL;
+  hipLaunchKernelGGL(k_head, dim3((n + 255) / 256), dim3(256), 0, S(stream), (const unsigned short*)h2, W3, b3, labels,
+                     n, wv, half_step, (unsigned short*)dh2, dW3, db3, loss);
+  return st_of(hipGetLastError());
+}
+
+rmdf_status rmdf_mlp_colsum(const void* in, int R, int C, float* out, void* stream) {
+  if (!in || !out || R < 1 || C < 1) return RMDF_E_INVAL;
+  hipLaunchKernelGGL(k_colsum, dim3(C), dim3(256), 0, S(stream), (const unsigned short*)in, R, C, out);
+  return st_of(hipGetLastError());
+}
+
+rmdf_status rmdf_mlp_infer_head(const void* h2, const float* W3, const float* b3, int n, float* vxyc, void* stream) {
+  if (!h2 || !W3 || !b3 || n < 1 || !vxyc) return RMDF_E_INVAL;
+  hipLaunchKernelGGL(k_infer_head, dim3((n + 255) / 256), dim3(256), 0, S(stream), (const unsigned short*)h2, W3, b3, n,
+                     vxyc);
+  return st_of(hipGetLastError());
+}
+
+rmdf_status rmdf_mlp_adam(float* p, const float* g, float* m, float* v, void* p_bf16, int n, float lr, float b1,
+                          float b2, float eps, int step, void* stream) {
+  if (!p || !g || !m || !v || n < 1 || step < 1) return RMDF_E_INVAL;
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, S(stream), p, g, m, v, (unsigned short*)p_bf16, n, lr,
+                     b1, b2, eps, c1, c2);
+  return st_of(hipGetLastError());
+}
+
+rmdf_status rmdf_mlp_to_bf16(const float* in, void* out, long long n, void* stream) {
+  if (!in || !out || n < 1) return RMDF_E_INVAL;
+  hipLaunchKernelGGL(k_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, S(stream), in, (unsigned short*)out, n);
+  return st_of(hipGetLastError());
+}
+
+}  // extern "C"

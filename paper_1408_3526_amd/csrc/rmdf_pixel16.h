@@ -96,6 +96,16 @@ constexpr size_t SMEM16 = sizeof(float2) * WAVES * SB_ELEMS + sizeof(float4) * 2
 
 // One work tile: 4 adjacent anchor columns starting at 4*xb (one per
 // wavefront), rows [yb*TY, yb*TY + TY).  All 256 threads must call it.
+static __device__ __forceinline__ unsigned short to_bf16(float f) {
+  unsigned int u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);      // round to nearest even (finite inputs)
+  return (unsigned short)(u >> 16);
+}
+
+// MODE: 0 plain search; 1 plain search that also writes the learned model's
+// input features; 2 learned mode (features, instantaneous search index for
+// the fallback; the background estimate is made later by finish16).
+template <int MODE>
 static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   float2* s_all = reinterpret_cast<float2*>(smem);
   float4* s_tab = reinterpret_cast<float4*>(smem + sizeof(float2) * WAVES * SB_ELEMS);  // tabB rows, then tabC rows
@@ -242,9 +252,11 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     // Planes -1 and 9 are the conjugate mirrors of planes 1 and 7:
     // S(-1, ky, kz) = conj S(1, -ky, -kz), S(9, ky, kz) = conj S(7, -ky, -kz).
     float2 QA, QB, Q8 = f2(0.f, 0.f);
+    float PA[MZ], PB[MZ], P8[MZ];
+#pragma unroll
+    for (int k = 0; k < MZ; ++k) P8[k] = 0.f;
     {
-      auto hxq = [&](const float2* Hc, int kx) -> float2 {
-        float P[MZ];
+      auto hxq = [&](const float2* Hc, int kx, float* P) -> float2 {
 #pragma unroll
         for (int k = 0; k < MZ; k += 2) {
           float4 l, rr, cc;
@@ -272,12 +284,46 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
         return stageA(P);
       };
       if (r == 0) {
-        QA = hxq(HA, 0);
-        Q8 = hxq(nullptr, 8);
+        QA = hxq(HA, 0, PA);
+        Q8 = hxq(nullptr, 8, P8);
       } else {
-        QA = hxq(HA, pA);
+        QA = hxq(HA, pA, PA);
       }
-      QB = hxq(HB, pB);
+      QB = hxq(HB, pB, PB);
+    }
+    if (MODE >= 1) {
+      // learned-model input: x = ln(P + eps) - mean over all Mx*My*Mz bins,
+      // eps = 1e-6 max P; stored for kx = 0..8 ([kx][ky][kz], BF16); bins
+      // with kx = 1..7 stand for their conjugate partner too (weight 2)
+      float mx = 0.f;
+#pragma unroll
+      for (int k = 0; k < MZ; ++k) mx = fmaxf(mx, fmaxf(PA[k], fmaxf(PB[k], r == 0 ? P8[k] : 0.f)));
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+      const float eps = fmaxf(1e-6f * mx, 1e-30f);
+      float sum = 0.f;
+#pragma unroll
+      for (int k = 0; k < MZ; ++k) {
+        PA[k] = __logf(PA[k] + eps);
+        PB[k] = __logf(PB[k] + eps);
+        P8[k] = (r == 0) ? __logf(P8[k] + eps) : 0.f;
+        sum += (r == 0 ? 1.f : 2.f) * PA[k] + 2.f * PB[k] + P8[k];
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+      const float mean = sum * (1.0f / (MX * MY * MZ));
+      unsigned short* fp = a.feat + pix * (NXH * MY * MZ);
+      auto put8 = [&](int kx, const float* L) {
+        uint4 u;
+        u.x = to_bf16(L[0] - mean) | ((unsigned int)to_bf16(L[1] - mean) << 16);
+        u.y = to_bf16(L[2] - mean) | ((unsigned int)to_bf16(L[3] - mean) << 16);
+        u.z = to_bf16(L[4] - mean) | ((unsigned int)to_bf16(L[5] - mean) << 16);
+        u.w = to_bf16(L[6] - mean) | ((unsigned int)to_bf16(L[7] - mean) << 16);
+        *reinterpret_cast<uint4*>(fp + (kx * MY + ky) * MZ) = u;
+      };
+      put8(pA, PA);
+      put8(pB, PB);
+      if (r == 0) put8(8, P8);
     }
     // even/odd split in ky for stage B: slot 0 = Q(0), slots 1..7 = Q(k)+Q(-k),
     // slot 8 = Q(8), slots 9..15 = Q(16-j) - Q(j-16)... stored by the lane of
@@ -343,9 +389,12 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
           rv += cC[kx - 1] * t.x - sC[kx - 1] * t.y;
         }
         const int w = iy * nvx + ixC;
-        float* rp = a.rsm + pix * nv + w;
-        const float sm = (1.f - a.alpha) * rv + a.alpha * (*rp);
-        *rp = sm;
+        float sm = rv;                     // learned mode: instantaneous R (no smoother state)
+        if (MODE != 2) {
+          float* rp = a.rsm + pix * nv + w;
+          sm = (1.f - a.alpha) * rv + a.alpha * (*rp);
+          *rp = sm;
+        }
         amax_merge(bv, bi, sm, w);
       }
     }
@@ -356,6 +405,10 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       amax_merge(bv, bi, v2, i2);
     }
     const int istar = (bi < nv) ? bi : 0;
+    if (MODE == 2) {
+      if (lane == 0) a.fidx[pix] = istar;
+      continue;
+    }
 
     // ---- background estimate with the chosen velocity's coefficients
     const int hsel = (a.vmode == 2) ? nv : istar;
@@ -391,6 +444,75 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
         a.vidx[pix] = istar;
       }
     }
+  }
+}
+
+// Background coefficient at (kx, ky centred, kz) for a continuous velocity:
+// eq. (8) at the DFT bins (the spatial Dirichlet factors select kx' = kx,
+// ky' = ky), times sqrt(Mz) (S = sqrt(Mz) X):
+//   D_Mz(kz/Mz + phi) / sqrt(Mx My Mz) * exp(j pi [-2(kx m'x/Mx + ky m'y/My)
+//   + 2 phi (m't - Dz) - 2 kz Dz/Mz]),  phi = vx kx/Mx + vy ky/My.
+static __device__ __forceinline__ float2 coeff16(int kx, int kyc, int kz, float vx, float vy, int dx, int dy, int dt) {
+  const float Dz = 0.5f * (MZ - 1);
+  const float phi = vx * kx * (1.0f / MX) + vy * kyc * (1.0f / MY);
+  const float w = kz * (1.0f / MZ) + phi;
+  const float rw = rintf(w);
+  float D;
+  if (fabsf(w - rw) < 1e-5f) D = (((int)rw * (MZ - 1)) & 1) ? -1.f : 1.f;
+  else D = sinpif(MZ * w) / (MZ * sinpif(w));
+  const float ph = -2.f * (kx * (float)dx / MX + kyc * (float)dy / MY) + 2.f * phi * (dt - Dz) - 2.f * kz * Dz / MZ;
+  float sn, cs;
+  sincospif(ph, &sn, &cs);
+  const float g = D * 0.0625f;        // sqrt(Mz) / sqrt(Mx My Mz) = 1/16
+  return f2(g * cs, g * sn);
+}
+
+// Learned mode, second pass: one wavefront per anchor.  Velocity = the
+// network's (vx, vy) where its confidence >= thr, else the search index
+// written by pixel16_tile<2>; background estimate and output.
+static __device__ void finish16(const PixArgs& a, const float* ring_delayed, const float* vc, float thr,
+                                int x, int y) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane >> 4, ky = lane & 15;
+  const int pA = r, pB = r + 4;
+  const size_t pix = (size_t)y * a.W + x;
+  const float conf = vc[3 * pix + 2];
+  const bool learned = conf >= thr;
+  const int fi = a.fidx[pix];
+  const float vx = learned ? vc[3 * pix] : a.gx[fi % a.nvx];
+  const float vy = learned ? vc[3 * pix + 1] : a.gy[fi / a.nvx];
+  float acc = 0.f;
+  const int kyc = (ky <= 8) ? ky : ky - 16;
+  if (kyc >= -a.by && kyc <= a.by) {
+    const float2* X = a.st + pix * NCOL * MZ;
+    for (int h = 0; h < 2; ++h) {
+      const int p = h ? pB : pA;
+      if (p > a.bx) continue;
+      const float2* xc = X + (p * MY + ky) * MZ;
+      const float wgt = (p == 0) ? 1.f : 2.f;
+      if (learned) {
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) {
+          const float2 c = coeff16(p, kyc, k, vx, vy, a.dx, a.dy, a.dt);
+          const float2 xv = xc[k];
+          acc += wgt * (c.x * xv.x - c.y * xv.y);
+        }
+      } else {
+        const float2* hp = a.htab + (((size_t)fi * (a.bx + 1) + p) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) acc += hp[k].x * xc[k].x - hp[k].y * xc[k].y;
+      }
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if (lane == 0) {
+    const int xs = x - a.dx, ys = y - a.dy;
+    float idel = (ring_delayed != nullptr && xs >= 0 && ys >= 0) ? ring_delayed[(size_t)ys * a.W + xs] : 0.f;
+    if (!isfinite(idel)) idel = 0.f;
+    a.out[pix] = idel - acc;
+    a.vxy[pix] = make_float2(vx, vy);
+    a.vidx[pix] = learned ? -2 : fi;
   }
 }
 

@@ -7,10 +7,17 @@
 namespace rmdf {
 namespace p16 {
 
+template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pixel16(PixArgs a) {
   __shared__ __align__(16) char smem[SMEM16];
   const int xblocks = (a.W + WAVES - 1) / WAVES;
-  pixel16_tile(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
+  pixel16_tile<MODE>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
+}
+
+__global__ void __launch_bounds__(256) k_finish16(PixArgs a, const float* vc, float thr) {
+  const long long pix = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (pix >= (long long)a.H * a.W) return;
+  finish16(a, a.ring_delayed, vc, thr, (int)(pix % a.W), (int)(pix / a.W));
 }
 
 }  // namespace p16
@@ -19,10 +26,18 @@ bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy) {
   return mx == 16 && my == 16 && mz == 8 && nvx <= p16::NV1_MAX && nvy <= p16::NV1_MAX;
 }
 
-hipError_t launch_pixel16(const PixArgs& a, hipStream_t s) {
+hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   const int xblocks = (a.W + p16::WAVES - 1) / p16::WAVES;
   const int yblocks = (a.H + a.TY - 1) / a.TY;
-  hipLaunchKernelGGL(p16::k_pixel16, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  if (mode == 0) hipLaunchKernelGGL(p16::k_pixel16<0>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else if (mode == 1) hipLaunchKernelGGL(p16::k_pixel16<1>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(p16::k_pixel16<2>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, hipStream_t s) {
+  const long long n = (long long)a.H * a.W;
+  hipLaunchKernelGGL(p16::k_finish16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, a, vc, thr);
   return hipGetLastError();
 }
 

@@ -1,0 +1,184 @@
+"""Learned velocity surrogate on the GPU: MFMA GEMM and training kernels
+against the FP64 reference (oracle/mlp.py), features against the oracle's
+power spectrum, and two closed-form pins of learned mode (a network that is
+never confident reduces to the unsmoothed search; a confident constant
+network reduces to the fixed-velocity filter)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import mlp  # noqa: E402
+from paper_1408_3526_amd import scenes  # noqa: E402
+
+
+def _b():
+    from paper_1408_3526_amd import binding
+    binding.lib()
+    return binding
+
+
+def _bf(a):
+    return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).cuda()
+
+
+@pytest.mark.parametrize("M,N,K", [(100, 70, 48), (64, 64, 32), (4096, 128, 1152), (37, 130, 200)])
+@pytest.mark.parametrize("epi", [0, 1, 2])
+def test_gemm_nt_matches_reference(M, N, K, epi):
+    b = _b()
+    rng = np.random.default_rng(M * 7 + N + K + epi)
+    A = mlp.bf16_round(rng.normal(size=(M, K)))
+    B = mlp.bf16_round(rng.normal(size=(N, K)))
+    bias = rng.normal(size=N).astype(np.float32)
+    aux = mlp.bf16_round(rng.normal(size=(M, N)))
+    C = torch.empty(M, N, device="cuda")
+    Cb = torch.empty(M, N, dtype=torch.bfloat16, device="cuda")
+    b.mlp_gemm_nt(_bf(A), _bf(B), bias=torch.from_numpy(bias).cuda(), epi=epi, aux=_bf(aux), out_f32=C, out_bf16=Cb)
+    torch.cuda.synchronize()
+    ref = A @ B.T + bias
+    if epi == 1:
+        ref = np.maximum(ref, 0)
+    elif epi == 2:
+        ref = np.where(aux > 0, ref, 0)
+    got = C.cpu().numpy().astype(np.float64)
+    scale = np.abs(A).max() * np.abs(B).max() * K
+    assert np.abs(got - ref).max() <= 1e-6 * scale
+    assert np.array_equal(Cb.cpu().float().numpy(), mlp.bf16_round(got.astype(np.float32)).astype(np.float32))
+
+
+def test_transpose():
+    b = _b()
+    x = torch.randn(77, 130, device="cuda").to(torch.bfloat16)
+    out = torch.empty(130, 77, dtype=torch.bfloat16, device="cuda")
+    b.mlp_transpose(x, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, x.t().contiguous())
+
+
+def test_training_gradients_match_reference():
+    from paper_1408_3526_amd import learned
+    rng = np.random.default_rng(3)
+    n = 512
+    X = mlp.bf16_round(rng.normal(size=(n, mlp.N_IN)))
+    lab = rng.uniform(-3, 3, size=(n, 2)).astype(np.float32)
+    tr = learned.Trainer(seed=1, batch=n)
+    params = [tr.p[k].cpu().numpy().astype(np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
+    # make the bias terms and the confidence head non-trivial
+    for k, i in (("b1", 1), ("b2", 3), ("b3", 5)):
+        params[i] = rng.normal(scale=0.1, size=params[i].shape)
+        tr.p[k].copy_(torch.from_numpy(params[i].astype(np.float32)))
+    loss = tr.grads(_bf(X), torch.from_numpy(lab).cuda())
+    torch.cuda.synchronize()
+    rl, rg = mlp.loss_and_grads(X, lab.astype(np.float64), params, wv=tr.wv, half_step=tr.half_step, bf16=True)
+    assert abs(float(loss.item()) - rl) <= 1e-3 * abs(rl)
+    for k, G in zip(("W1", "b1", "W2", "b2", "W3", "b3"), rg):
+        g = tr.g[k].cpu().numpy().astype(np.float64)
+        rel = np.linalg.norm(g - G) / max(np.linalg.norm(G), 1e-30)
+        assert rel <= 1e-2, (k, rel)
+
+
+def test_adam_step():
+    b = _b()
+    rng = np.random.default_rng(4)
+    p = rng.normal(size=1000).astype(np.float32)
+    g = rng.normal(size=1000).astype(np.float32)
+    m = rng.normal(size=1000).astype(np.float32) * 0.1
+    v = np.abs(rng.normal(size=1000)).astype(np.float32) * 0.1
+    tp, tg, tm, tv = (torch.from_numpy(a.copy()).cuda() for a in (p, g, m, v))
+    pb = torch.empty(1000, dtype=torch.bfloat16, device="cuda")
+    b.mlp_adam(tp, tg, tm, tv, pb, lr=1e-2, step=3)
+    torch.cuda.synchronize()
+    m2 = 0.9 * m + 0.1 * g
+    v2 = 0.999 * v + 0.001 * g * g
+    ref = p - 1e-2 * (m2 / (1 - 0.9 ** 3)) / (np.sqrt(v2 / (1 - 0.999 ** 3)) + 1e-8)
+    assert np.abs(tp.cpu().numpy() - ref).max() <= 1e-5
+    assert torch.equal(pb, tp.to(torch.bfloat16))
+
+
+def test_features_match_oracle(orc):
+    b = _b()
+    sc = scenes.flow_scene(5, H=36, W=40, T=10, n_targets=2, band_width=(6, 9))
+    g = scenes.grid(-4, 4, 0.5)
+    f = b.Filter(36, 40, 16, 16, 8, g, g, write_features=True)
+    dev = torch.from_numpy(sc.frames).cuda()
+    for t in range(10):
+        f.push_frame(dev[t])
+    F = f.features().float().cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+    cfg = orc.Cfg(H=36, W=40, Mx=16, My=16, Mz=8, gx=g, gy=g)
+    pts = [(39, 35), (20, 20), (15, 30), (0, 0), (5, 33)]
+    errs = []
+    for (x, y) in pts:
+        p = orc.pixel_series(cfg, sc.frames, x, y)
+        _, P = orc.flow_R(cfg, p["S"][-1], want_P=True)
+        ref = mlp.features_from_P(P)
+        errs.append(np.abs(F[y, x] - ref) / (0.05 + 0.01 * np.abs(ref)))
+    e = np.concatenate(errs)
+    assert np.quantile(e, 0.995) <= 1.0 and np.median(e) <= 0.2, (np.quantile(e, 0.995), np.median(e))
+
+
+def _blob(b3):
+    w = np.zeros(mlp.N_H1 * mlp.N_IN + mlp.N_H1 + mlp.N_H2 * mlp.N_H1 + mlp.N_H2 + 3 * mlp.N_H2 + 3, np.float32)
+    w[-3:] = b3
+    return w
+
+
+def test_learned_never_confident_is_unsmoothed_search(orc):
+    b = _b()
+    sc = scenes.flow_scene(6, H=34, W=37, T=11, n_targets=2, band_width=(6, 9))
+    g = scenes.grid(-4, 4, 0.5)
+    f = b.Filter(34, 37, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9)
+    f.set_weights(_blob([0.0, 0.0, -20.0]))
+    dev = torch.from_numpy(sc.frames).cuda()
+    for t in range(11):
+        f.push_frame(dev[t])
+    out = f.output().cpu().numpy()
+    _, idx = f.velocity()
+    idx = idx.cpu().numpy()
+    vc = f.learned_output().cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+    assert np.all(vc[..., 2] < 1e-6) and np.all(idx >= 0)
+    r = orc.run(orc.Cfg(H=34, W=37, Mx=16, My=16, Mz=8, gx=g, gy=g, alpha=0.0), sc.frames, want_rs=True)
+    rs = r["rs_all"][-1]
+    srt = np.sort(rs, -1)
+    scale = np.maximum(np.maximum(np.abs(rs).max(-1), 1e-3 * r["en_all"][-1]), 1e-30)
+    tied = srt[..., -1] - srt[..., -2] <= 1e-4 * scale
+    agree = idx == r["idx"][-1]
+    assert agree[~tied].mean() >= 0.999
+    rms = float(np.sqrt(np.mean(sc.frames[-1].astype(np.float64) ** 2)))
+    assert np.abs(out - r["out"][-1])[agree].max() <= 1e-3 * rms
+
+
+def test_learned_confident_constant_is_fixed_velocity(orc):
+    b = _b()
+    sc = scenes.flow_scene(7, H=34, W=37, T=11, n_targets=2, band_width=(6, 9))
+    g = scenes.grid(-4, 4, 0.5)
+    v = (1.3, -0.7)
+    f = b.Filter(34, 37, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9)
+    f.set_weights(_blob([v[0], v[1], 20.0]))
+    dev = torch.from_numpy(sc.frames).cuda()
+    outs = []
+    for t in range(11):
+        f.push_frame(dev[t])
+        outs.append(f.output().cpu().numpy())
+    vxy, idx = f.velocity()
+    vxy, idx = vxy.cpu().numpy(), idx.cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+    assert np.all(idx == -2)
+    assert np.allclose(vxy[..., 0], v[0]) and np.allclose(vxy[..., 1], v[1])
+    r = orc.run(orc.Cfg(H=34, W=37, Mx=16, My=16, Mz=8, gx=g, gy=g, vmode=2, fvx=v[0], fvy=v[1]), sc.frames)
+    for t in range(11):
+        rms = float(np.sqrt(np.mean(sc.frames[t].astype(np.float64) ** 2)))
+        assert np.abs(outs[t] - r["out"][t]).max() <= 1e-3 * rms, t
+
+
+def test_short_training_reduces_loss():
+    from paper_1408_3526_amd import learned
+    X, lab, true = learned.harvest([11, 12], H=64, W=80, T=14, per_seq=2500)
+    assert X.shape == (5000, 1152) and lab.shape == (5000, 2)
+    tr, losses = learned.train(X, lab, steps=300, batch=1024)
+    assert losses[-1][1] < 0.7 * losses[0][1], losses
