@@ -22,6 +22,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 
+# HBM bytes per launch of the per-pixel kernel, measured with rocprofv3 PMC
+# counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
+# reads for a plain copy of known size).  The figure only stands for the
+# kernel source it was taken on: a change to any of these files voids it.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pixel16_640x512.txt")
+KERNEL_SOURCES = ["paper_1408_3526_amd/csrc/rmdf_pixel16.h", "paper_1408_3526_amd/csrc/rmdf_pixel16.hip",
+                  "paper_1408_3526_amd/csrc/rmdf_kernels.h"]
+
 WORKLOADS = {
     "640x512": dict(H=512, W=640, M=(16, 16, 8), grid=(-4.0, 4.0, 0.5), frames=200, seed=1, targets=20),
     "1280x1024": dict(H=1024, W=1280, M=(16, 16, 8), grid=(-4.0, 4.0, 0.5), frames=100, seed=2, targets=50),
@@ -36,6 +44,43 @@ def algorithmic_bytes_per_pixel_frame(M, nv):
     output out, velocity (2 FP32) out."""
     Mx, My, Mz = M
     return 2 * 4 * Mx * My * Mz + 2 * 4 * nv + 4 + 4 + 4 + 8
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kname, workload):
+    """HBM bytes per launch from the committed counter summary, or None when
+    it is absent or was taken on another kernel, workload or source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split("=", 1) for line in (ln.strip() for ln in f) if "=" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if (kv.get("kernel") != kname or kv.get("workload") != workload
+            or kv.get("source_sha256") != kernel_source_digest()):
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def copy_calibration(nbytes=1 << 30, reps=10):
+    """A plain device copy of known size, for scaling the PMC byte counters:
+    each launch reads and writes nbytes."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
+                      "launches": reps}), flush=True)
 
 
 def make_frames(wl):
@@ -75,11 +120,16 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 generic, 2 wave-per-anchor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a 1 GiB device copy (the reference kernel for the PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the per-pixel state shards by row strips; see the design notes)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
 
     import numpy as np
     import torch
@@ -148,7 +198,7 @@ def main():
                                "plain autocorrelation search" % (W, H, M[0], M[1], M[2], len(g), len(g), g[1] - g[0]),
                    "frames_distinct": int(T), "tile_rows": args.tile_rows or 32},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, args.workload),
                      "kernel": kname, "kernel_ms": pix_ms,
                      "algorithmic_bytes_per_pixel_frame": bpp},
         "kernel_ms": {"pixel": pix_ms, "row": kms[1][0] / max(kms[1][1], 1), "ingest": kms[2][0] / max(kms[2][1], 1)},

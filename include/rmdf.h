@@ -184,6 +184,15 @@ rmdf_status rmdf_mlp_to_bf16(const float *in, void *out_bf16, long long n, void 
  * per anchor), after resolving kernel_variant = 0. */
 rmdf_status rmdf_kernel_variant(const rmdf_ctx *ctx, int *variant);
 
+/* How the wavefront-per-anchor kernel stores the background coefficients of
+ * eq. (8): *lattice_q = 16 s when every candidate velocity (and the fixed
+ * velocity in RMDF_VEL_FIXED mode) is a whole multiple of 1/s px/frame for
+ * s in {1, 2, 4}; the coefficients then factor into a spatial phase per
+ * (kx, ky) and a 16 s x Kt table of the temporal part, held in LDS.
+ * *lattice_q = 0: a per-candidate table in device memory is read instead
+ * (any other grid, or the generic kernel). */
+rmdf_status rmdf_coeff_lattice(const rmdf_ctx *ctx, int *lattice_q);
+
 /* Bytes of device memory the context holds. */
 rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);
 
@@ -210,7 +219,10 @@ typedef struct {
 rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc *streams, const rmdf_params *p,
                               void *hip_stream, rmdf_batch **out);
 /* Device address where the next frame of stream s (H*W FP32) must be written
- * before rmdf_batch_launch (zero-copy input). */
+ * before rmdf_batch_launch (zero-copy input).  The write must be complete, or
+ * ordered before the launch on the batch's stream, when the launch is made:
+ * the batch stream does not wait for work on other streams (a device-to-device
+ * hipMemcpy may return before the copy has finished). */
 rmdf_status rmdf_batch_input(rmdf_batch *b, int s, float **frame_dev);
 /* Advance every stream by one frame (one graph launch). */
 rmdf_status rmdf_batch_launch(rmdf_batch *b);

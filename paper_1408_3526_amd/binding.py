@@ -57,6 +57,7 @@ _SIGS = {
     "rmdf_kernel_time": (_I, [_VP, _I, ctypes.POINTER(_D), ctypes.POINTER(_LL)]),
     "rmdf_device_bytes": (_I, [_VP, ctypes.POINTER(_SZ)]),
     "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
+    "rmdf_coeff_lattice": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
     "rmdf_mlp_set_weights": (_I, [_VP, _VP, _SZ]),
@@ -277,6 +278,13 @@ class Filter:
         Mx, My, Mz = self.M
         return "k_pixel16" if v.value == 2 else "k_pixel<%d,%d,%d>" % (Mx, My, Mz)
 
+    def coeff_lattice(self) -> int:
+        """16 s when the background coefficients use the lattice table (grid
+        step 1/s px/frame), else 0."""
+        q = ctypes.c_int()
+        _check(lib().rmdf_coeff_lattice(self.ctx, ctypes.byref(q)), self.ctx)
+        return q.value
+
     def frames_pushed(self) -> int:
         n = ctypes.c_longlong()
         _check(lib().rmdf_frames_pushed(self.ctx, ctypes.byref(n)), self.ctx)
@@ -336,6 +344,8 @@ class Batch:
         if stream is None:
             self.torch_stream = torch.cuda.Stream()
             stream = self.torch_stream.cuda_stream
+        else:
+            self.torch_stream = torch.cuda.ExternalStream(int(stream))
         self.stream_handle = int(stream)
         self.b = _VP()
         _bcheck(lib().rmdf_batch_create(len(streams), descs, ctypes.byref(p), ctypes.c_void_p(self.stream_handle),
@@ -348,7 +358,12 @@ class Batch:
         _bcheck(lib().rmdf_batch_input(self.b, int(s), ctypes.byref(ptr)), self.b)
         return ptr.value
 
+    # The batch runs on its own stream: work the caller queued on torch's
+    # current stream (frames written, output buffers freed) is ordered before
+    # each call, and outputs are ordered back onto the current stream.
     def launch(self):
+        import torch
+        self.torch_stream.wait_stream(torch.cuda.current_stream())
         _bcheck(lib().rmdf_batch_launch(self.b), self.b)
 
     def push(self, frames):
@@ -357,7 +372,10 @@ class Batch:
         for i, fr in enumerate(frames):
             sp = self.specs[i]
             ptrs[i] = _dev_ptr(fr, torch.float32, sp["H"] * sp["W"], "frame %d" % i)
+        self.torch_stream.wait_stream(torch.cuda.current_stream())
         _bcheck(lib().rmdf_batch_push(self.b, ptrs), self.b)
+        for fr in frames:
+            fr.record_stream(self.torch_stream)
 
     def output(self, s: int):
         import torch
@@ -365,7 +383,12 @@ class Batch:
         out = torch.empty((sp["H"], sp["W"]), dtype=torch.float32, device="cuda")
         vxy = torch.empty((sp["H"], sp["W"], 2), dtype=torch.float32, device="cuda")
         idx = torch.empty((sp["H"], sp["W"]), dtype=torch.int32, device="cuda")
+        cur = torch.cuda.current_stream()
+        self.torch_stream.wait_stream(cur)
         _bcheck(lib().rmdf_batch_output(self.b, int(s), out.data_ptr(), vxy.data_ptr(), idx.data_ptr()), self.b)
+        cur.wait_stream(self.torch_stream)
+        for x in (out, vxy, idx):
+            x.record_stream(self.torch_stream)
         return out, vxy, idx
 
     def set_tiles(self, s: int, tile_rows: int):

@@ -3,11 +3,13 @@
 //   k_row_batch        row sliding DFT of every stream (one block per
 //                      (stream, row, chunk)); reads each stream's raw frame from
 //                      its delay-ring slot, non-finite samples read as 0
-//   k_batch_persistent one persistent workgroup per resident slot pulls
-//                      (stream, tile) items from an atomic queue ordered by
-//                      decreasing cost and runs that stream's per-pixel tile;
-//                      the last workgroup to finish advances every stream's
-//                      frame counter and re-arms the queue for the next step
+//   k_batch_p16        persistent workgroups pull (stream, tile) items of the
+//   k_batch_generic    16x16x8 wave-per-anchor streams (resp. all other
+//                      windows) from an atomic queue ordered by decreasing
+//                      cost and run that stream's per-pixel tile; one kernel
+//                      per tile family, so each gets its own register budget
+//   k_batch_advance    advances every stream's frame counter and re-arms the
+//                      queues for the next step
 // Nothing in the graph changes between steps: frame counters live in device
 // memory and frames are written into the ring slots before each launch.
 #include <hip/hip_runtime.h>
@@ -27,7 +29,7 @@
 
 namespace rmdf {
 
-enum : int { KIND_884 = 0, KIND_995 = 1, KIND_16G = 2, KIND_16W = 3 };
+enum : int { KIND_884 = 0, KIND_995 = 1, KIND_16G = 2, KIND_16W = 3, NKIND = 4 };
 
 struct RowDesc {
   const float* ring;                 // stream's delay ring
@@ -49,14 +51,11 @@ struct BatchPixDesc {
 
 struct BatchState {
   long long* t;                      // [n] frames pushed per stream (device)
-  unsigned int* queue;               // next work item
-  unsigned int* done;                // finished workgroups
+  unsigned int* queue;               // [NKIND] next work item of each tile family
 };
 
 constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 constexpr size_t ROW_SMEM = cmax(cmax(RowShape<8>::SMEM, RowShape<16>::SMEM), RowShape<9>::SMEM);
-constexpr size_t PIX_SMEM = cmax(cmax(cmax(Shape<8, 8, 4>::SMEM, Shape<9, 9, 5>::SMEM), Shape<16, 16, 8>::SMEM),
-                                 p16::SMEM16);
 
 __global__ void __launch_bounds__(256) k_row_batch(const RowDesc* __restrict__ d, int n, const long long* __restrict__ t) {
   __shared__ __align__(16) char smem[ROW_SMEM];
@@ -71,48 +70,57 @@ __global__ void __launch_bounds__(256) k_row_batch(const RowDesc* __restrict__ d
   else row_chunk<9>(f, r.rs, r.twx, r.H, r.W, y, x0, smem, r.nonfinite);
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
-k_batch_persistent(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items, int n_streams,
-                   BatchState bs) {
-  __shared__ __align__(16) char smem[PIX_SMEM];
-  __shared__ unsigned int s_item;
+// Item loop shared by both persistent kernels: claim the next item, run its
+// tile, until the family's queue is empty.
+template <class F>
+static __device__ void item_loop(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items,
+                                 unsigned int* queue, const long long* t, unsigned int* s_item, F&& run) {
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(bs.queue, 1u);
+    if (threadIdx.x == 0) *s_item = atomicAdd(queue, 1u);
     __syncthreads();
-    const unsigned int it = s_item;
+    const unsigned int it = *s_item;
     __syncthreads();                    // all have read s_item before it is overwritten
     if (it >= (unsigned int)n_items) break;
     const int4 w = items[it];
     const BatchPixDesc& bd = d[w.x];
-    const long long tt = bs.t[w.x];
+    const long long tt = t[w.x];
     const float* rd = (tt >= bd.dt) ? bd.ring + (size_t)((tt - bd.dt) % bd.nring) * bd.hw : nullptr;
-    switch (bd.kind) {
-      case KIND_884: pixel_tile<8, 8, 4>(bd.a, rd, w.y, w.z, smem); break;
-      case KIND_995: pixel_tile<9, 9, 5>(bd.a, rd, w.y, w.z, smem); break;
-      case KIND_16G: pixel_tile<16, 16, 8>(bd.a, rd, w.y, w.z, smem); break;
-      default: p16::pixel16_tile<0>(bd.a, rd, w.y, w.z, smem); break;
-    }
-  }
-  // the last workgroup out advances the frame counters and re-arms the queue
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned int prev = atomicAdd(bs.done, 1u);
-    if (prev == gridDim.x - 1) {
-      for (int s = 0; s < n_streams; ++s) bs.t[s] += 1;
-      *bs.queue = 0u;
-      *bs.done = 0u;
-      __threadfence();
-    }
+    run(bd, rd, w);
   }
 }
 
-// Zeroes the queue and completion counters (a kernel, not a memset, so the
-// same code is safe to capture).
+template <int KIND> struct KindSmem;
+template <> struct KindSmem<KIND_884> { static constexpr size_t v = Shape<8, 8, 4>::SMEM; };
+template <> struct KindSmem<KIND_995> { static constexpr size_t v = Shape<9, 9, 5>::SMEM; };
+template <> struct KindSmem<KIND_16G> { static constexpr size_t v = Shape<16, 16, 8>::SMEM; };
+template <> struct KindSmem<KIND_16W> { static constexpr size_t v = p16::SMEM16; };
+
+// One persistent kernel per tile family (its queue is queue[KIND]); the
+// 16x16x8 wave-per-anchor tile gets the register budget of three resident
+// workgroups per CU, as in the single-stream kernel.
+template <int KIND>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIND_16W ? 3 : 1)))
+k_batch_tiles(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items, BatchState bs) {
+  __shared__ __align__(16) char smem[KindSmem<KIND>::v];
+  __shared__ unsigned int s_item;
+  item_loop(d, items, n_items, bs.queue + KIND, bs.t, &s_item, [&](const BatchPixDesc& bd, const float* rd, int4 w) {
+    if (KIND == KIND_884) pixel_tile<8, 8, 4>(bd.a, rd, w.y, w.z, smem);
+    else if (KIND == KIND_995) pixel_tile<9, 9, 5>(bd.a, rd, w.y, w.z, smem);
+    else if (KIND == KIND_16G) pixel_tile<16, 16, 8>(bd.a, rd, w.y, w.z, smem);
+    else p16::pixel16_tile<0>(bd.a, rd, w.y, w.z, smem);
+  });
+}
+
+// End of a step: every stream has consumed one frame; re-arm the queues (a
+// kernel, not a memset, so the same code is safe to capture).
+__global__ void k_batch_advance(BatchState bs, int n_streams) {
+  for (int s = threadIdx.x; s < n_streams; s += blockDim.x) bs.t[s] += 1;
+  if (threadIdx.x < NKIND) bs.queue[threadIdx.x] = 0u;
+}
+
+// Zeroes the queues before the first step.
 __global__ void k_batch_arm(BatchState bs) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *bs.queue = 0u;
-    *bs.done = 0u;
-  }
+  if (threadIdx.x < NKIND) bs.queue[threadIdx.x] = 0u;
 }
 
 }  // namespace rmdf
@@ -126,15 +134,15 @@ struct rmdf_batch {
   bool own_stream = false;
   std::vector<int> tile_rows;        // per stream
   int grid_mult = 1;                 // persistent workgroups per resident slot
-  int persistent_blocks = 0;
   // device
   RowDesc* d_row = nullptr;
   BatchPixDesc* d_pix = nullptr;
   int4* d_items = nullptr;
   long long* d_t = nullptr;
-  unsigned int* d_queue = nullptr;
-  unsigned int* d_done = nullptr;
-  int n_items = 0, row_blocks = 0;
+  unsigned int* d_queue = nullptr;   // [NKIND]
+  int row_blocks = 0;
+  int n_items[NKIND] = {};           // work items of each tile family
+  int blocks[NKIND] = {};            // persistent workgroups of each family's kernel
   std::vector<long long> t;          // host mirror of the frame counters
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -193,29 +201,57 @@ static hipError_t rebuild(rmdf_batch* b) {
         items.push_back({make_int4(s, xb, yb, 0), per_px * rows * colsn});
       }
   }
-  // longest first, so the tail of the step is made of small items
-  std::stable_sort(items.begin(), items.end(), [](const Item& p, const Item& q) { return p.cost > q.cost; });
+  // grouped by tile family, each group longest first so the tail of its
+  // kernel is made of small items
+  std::stable_sort(items.begin(), items.end(), [&](const Item& p, const Item& q) {
+    const int fp = pd[p.w.x].kind, fq = pd[q.w.x].kind;
+    if (fp != fq) return fp < fq;
+    return p.cost > q.cost;
+  });
   std::vector<int4> iv(items.size());
-  for (size_t i = 0; i < items.size(); ++i) iv[i] = items[i].w;
+  for (int k = 0; k < NKIND; ++k) b->n_items[k] = 0;
+  for (size_t i = 0; i < items.size(); ++i) {
+    iv[i] = items[i].w;
+    b->n_items[pd[items[i].w.x].kind] += 1;
+  }
   if (b->d_items) hipFree(b->d_items);
   b->d_items = nullptr;
   if ((e = hipMalloc(&b->d_items, sizeof(int4) * std::max<size_t>(iv.size(), 1))) != hipSuccess) return e;
   if ((e = hipMemcpy(b->d_items, iv.data(), sizeof(int4) * iv.size(), hipMemcpyHostToDevice)) != hipSuccess) return e;
   if ((e = hipMemcpy(b->d_pix, pd.data(), sizeof(BatchPixDesc) * b->n, hipMemcpyHostToDevice)) != hipSuccess) return e;
-  b->n_items = (int)iv.size();
 
-  int dev = 0, cus = 0, occ = 0;
+  int dev = 0, cus = 0;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_batch_persistent), 256, 0);
-  b->persistent_blocks = std::max(1, std::min(b->n_items, cus * std::max(occ, 1) * b->grid_mult));
+  const void* kern[NKIND] = {reinterpret_cast<const void*>(k_batch_tiles<KIND_884>),
+                             reinterpret_cast<const void*>(k_batch_tiles<KIND_995>),
+                             reinterpret_cast<const void*>(k_batch_tiles<KIND_16G>),
+                             reinterpret_cast<const void*>(k_batch_tiles<KIND_16W>)};
+  for (int k = 0; k < NKIND; ++k) {
+    int occ = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern[k], 256, 0);
+    b->blocks[k] = std::min(b->n_items[k], cus * std::max(occ, 1) * b->grid_mult);
+  }
 
-  BatchState bs{b->d_t, b->d_queue, b->d_done};
+  BatchState bs{b->d_t, b->d_queue};
   if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_batch, dim3(b->row_blocks), dim3(256), 0, b->stream, b->d_row, b->n,
                      (const long long*)b->d_t);
-  hipLaunchKernelGGL(k_batch_persistent, dim3(b->persistent_blocks), dim3(256), 0, b->stream, b->d_pix,
-                     (const int4*)b->d_items, b->n_items, b->n, bs);
+  // the largest tiles first
+  const int order[NKIND] = {KIND_16W, KIND_16G, KIND_995, KIND_884};
+  for (int k : order) {
+    if (b->blocks[k] == 0) continue;
+    int first = 0;
+    for (int j = 0; j < k; ++j) first += b->n_items[j];
+    const int4* it = (const int4*)b->d_items + first;
+    switch (k) {
+      case KIND_884: hipLaunchKernelGGL(k_batch_tiles<KIND_884>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
+      case KIND_995: hipLaunchKernelGGL(k_batch_tiles<KIND_995>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
+      case KIND_16G: hipLaunchKernelGGL(k_batch_tiles<KIND_16G>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
+      default: hipLaunchKernelGGL(k_batch_tiles<KIND_16W>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
+    }
+  }
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(256), 0, b->stream, bs, b->n);
   if ((e = hipStreamEndCapture(b->stream, &b->graph)) != hipSuccess) return e;
   if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) return e;
   return hipSuccess;
@@ -281,11 +317,10 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
   if ((e = hipMalloc(&b->d_row, sizeof(RowDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
   if ((e = hipMalloc(&b->d_pix, sizeof(BatchPixDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
   if ((e = hipMalloc(&b->d_t, sizeof(long long) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
-  if ((e = hipMalloc(&b->d_queue, sizeof(unsigned int))) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
-  if ((e = hipMalloc(&b->d_done, sizeof(unsigned int))) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
+  if ((e = hipMalloc(&b->d_queue, NKIND * sizeof(unsigned int))) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
   hipMemcpy(b->d_row, rd.data(), sizeof(RowDesc) * n, hipMemcpyHostToDevice);
   hipMemcpy(b->d_t, b->t.data(), sizeof(long long) * n, hipMemcpyHostToDevice);
-  hipLaunchKernelGGL(k_batch_arm, dim3(1), dim3(64), 0, b->stream, BatchState{b->d_t, b->d_queue, b->d_done});
+  hipLaunchKernelGGL(k_batch_arm, dim3(1), dim3(64), 0, b->stream, BatchState{b->d_t, b->d_queue});
   if ((e = rebuild(b)) != hipSuccess) return bail(RMDF_E_DEVICE, std::string("graph: ") + hipGetErrorString(e));
   if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return bail(RMDF_E_DEVICE, "sync");
   *out = b;
@@ -474,7 +509,6 @@ rmdf_status rmdf_batch_destroy(rmdf_batch* b) {
   hipFree(b->d_pix);
   hipFree(b->d_t);
   hipFree(b->d_queue);
-  hipFree(b->d_done);
   for (auto* c : b->ctx) rmdf_destroy(c);
   if (b->own_stream) hipStreamDestroy(b->stream);
   delete b;

@@ -47,6 +47,9 @@ struct rmdf_ctx {
   int* vidx = nullptr;
   float2 *twx = nullptr, *twy = nullptr, *twz = nullptr, *twA = nullptr;
   float2 *tauy = nullptr, *taux = nullptr, *htab = nullptr;
+  float2 *gtab = nullptr, *etab = nullptr;   // lattice factors of htab (16x16x8)
+  int* latq = nullptr;
+  int lat_q = 0;
   float *gx = nullptr, *gy = nullptr, *tabB = nullptr, *tabC = nullptr;
   int variant = 0;                 // resolved kernel variant (1 generic, 2 wave-per-anchor)
   int write_features = 0;          // plain search that also writes the learned-model input
@@ -190,6 +193,54 @@ static hipError_t build_tables(rmdf_ctx* c, const float* gxh, const float* gyh) 
         }
   }
   if ((e = upload(c, &c->htab, htab)) != hipSuccess) return e;
+  // Lattice factorisation of the same coefficients.  With phi = vx kx/Mx +
+  // vy ky/My the coefficient is E(kx, ky) G(phi, kz), E carrying the spatial
+  // delay phase and the Hermitian weight, G the temporal part (Dirichlet
+  // kernel and phase); G is 1-periodic in phi (the sign of D_Mz(w + 1) and of
+  // exp(j 2 pi (m't - Dz)) cancel).  If s*v is an integer for every velocity
+  // used (s in {1, 2, 4}), phi = (nx kx + ny ky) / (16 s) mod 1 takes 16 s
+  // values, and G becomes a 16s x Mz table.
+  if (c->MX == 16 && c->MY == 16 && c->MZ == 8 && c->Bx <= 7 && c->By <= 8) {
+    auto on_lattice = [](double v, int s) {
+      return std::fabs(v * s) < 16384.0 && std::fabs(v * s - std::nearbyint(v * s)) < 1e-9;
+    };
+    int s_ok = 0;
+    for (int s = 1; s <= 4 && !s_ok; s *= 2) {
+      bool ok = true;
+      for (int i = 0; i < c->nvx && ok; ++i) ok = on_lattice(gxh[i], s);
+      for (int i = 0; i < c->nvy && ok; ++i) ok = on_lattice(gyh[i], s);
+      if (c->vmode == 2) ok = ok && on_lattice(c->fvx, s) && on_lattice(c->fvy, s);
+      if (ok) s_ok = s;
+    }
+    if (s_ok) {
+      const int Q = 16 * s_ok;
+      const double N = 16.0 * 16.0 * 8.0, Dz = 3.5;
+      std::vector<float2> gt((size_t)Q * 8), et((size_t)nbx * nby);
+      for (int q = 0; q < Q; ++q)
+        for (int kz = 0; kz < 8; ++kz) {
+          const double phi = (double)q / Q;
+          const double ph = 2.0 * kPi * (phi * (c->dt - Dz) - kz * Dz / 8.0);
+          gt[(size_t)q * 8 + kz] = f2(sz * dirichlet(8, kz / 8.0 + phi) / std::sqrt(N) * cd(std::cos(ph), std::sin(ph)));
+        }
+      for (int kx = 0; kx < nbx; ++kx)
+        for (int j = 0; j < nby; ++j) {
+          const double w = (kx == 0) ? 1.0 : 2.0;
+          const double ph = -2.0 * kPi * ((double)kx * c->dx / 16.0 + (double)(j - c->By) * c->dy / 16.0);
+          et[(size_t)kx * nby + j] = f2(w * cd(std::cos(ph), std::sin(ph)));
+        }
+      std::vector<int> lq((size_t)c->nv + 1);
+      for (int i = 0; i <= c->nv; ++i) {
+        const double vx = (i < c->nv) ? gxh[i % c->nvx] : c->fvx;
+        const double vy = (i < c->nv) ? gyh[i / c->nvx] : c->fvy;
+        const int nx = (int)std::nearbyint(vx * s_ok), ny = (int)std::nearbyint(vy * s_ok);
+        lq[i] = (int)(((unsigned)nx << 16) | ((unsigned)ny & 0xffffu));
+      }
+      if ((e = upload(c, &c->gtab, gt)) != hipSuccess) return e;
+      if ((e = upload(c, &c->etab, et)) != hipSuccess) return e;
+      if ((e = upload(c, &c->latq, lq)) != hipSuccess) return e;
+      c->lat_q = Q;
+    }
+  }
   // register-resident weights of the wave-per-anchor 16x16x8 kernel: along
   // ky, cos and sin of 2 pi k l / 16 for k = 1..7 and cos(pi l) (Nyquist);
   // along kx the same with the Hermitian factor 2 folded in
@@ -232,6 +283,7 @@ rmdf::PixArgs rmdf_internal_pixargs(const rmdf_ctx* c) {
   a.twy = c->twy; a.twz = c->twz; a.twA = c->twA; a.tauy = c->tauy; a.taux = c->taux; a.htab = c->htab;
   a.gx = c->gx; a.gy = c->gy; a.tabB = c->tabB; a.tabC = c->tabC;
   a.feat = c->feat; a.fidx = c->fidx; a.dt = c->dt;
+  a.gtab = c->gtab; a.etab = c->etab; a.latq = c->latq; a.lat_q = c->lat_q;
   return a;
 }
 const float* rmdf_internal_ring(const rmdf_ctx* c, int* nring, int* dt) {
@@ -580,6 +632,12 @@ rmdf_status rmdf_learned_output(rmdf_ctx* c, float* vc_dev) {
 rmdf_status rmdf_kernel_variant(const rmdf_ctx* c, int* variant) {
   if (!c || !variant) return RMDF_E_INVAL;
   *variant = c->variant;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_coeff_lattice(const rmdf_ctx* c, int* lattice_q) {
+  if (!c || !lattice_q) return RMDF_E_INVAL;
+  *lattice_q = (c->variant == 2) ? c->lat_q : 0;
   return RMDF_OK;
 }
 

@@ -38,6 +38,14 @@ struct PixArgs {
   unsigned short* feat;        // [H][W][9][16][8] BF16 learned-model features (16x16x8), or nullptr
   int* fidx;                   // [H][W] search index for the learned-mode fallback
   int dt;                      // temporal output delay
+  // Lattice form of the background coefficients (16x16x8 kernel): when every
+  // candidate velocity v satisfies v*s integral for s in {1, 2, 4}, the
+  // coefficient at (kx, ky, kz) factors as etab[kx][ky+by] * gtab[q][kz] with
+  // q = (nx kx + ny ky) mod 16s, (nx, ny) = s*v.  gtab == nullptr: no lattice.
+  const float2* gtab;          // [16s][Mz]
+  const float2* etab;          // [bx+1][2by+1]
+  const int* latq;             // [nv+1] (nx << 16) | (ny & 0xffff); entry nv = fixed velocity
+  int lat_q;                   // 16s
 };
 
 bool shape_supported(int mx, int my, int mz);

@@ -38,6 +38,25 @@ constexpr int NV1_MAX = 21;       // 3 lane groups x 21 <= 64
 
 static __device__ __forceinline__ float2 f2(float x, float y) { return make_float2(x, y); }
 
+// LDS pointers keep their address space so every access is a ds_* instruction
+// with an immediate offset (a generic pointer would become a flat access)
+#define RMDF_LDS __attribute__((address_space(3)))
+#define RMDF_GLOBAL __attribute__((address_space(1)))
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef RMDF_LDS v2f lds_v2;
+typedef RMDF_LDS v4f lds_v4;
+typedef RMDF_LDS float lds_float;
+__device__ __forceinline__ float2 ld2(const lds_v2* p) { const v2f v = *p; return make_float2(v.x, v.y); }
+__device__ __forceinline__ float4 ld4(const lds_v2* p) {
+  const v4f v = *reinterpret_cast<const lds_v4*>(p);
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st2(lds_v2* p, float2 v) { *p = v2f{v.x, v.y}; }
+__device__ __forceinline__ void st4(lds_v2* p, float a, float b, float c, float d) {
+  *reinterpret_cast<lds_v4*>(p) = v4f{a, b, c, d};
+}
+
 template <int CTRL>
 static __device__ __forceinline__ float dppf(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
@@ -80,7 +99,9 @@ static __device__ __forceinline__ float2 rot8(float2 a, int k) {
 }
 
 static __device__ __forceinline__ void amax_merge(float& v, int& i, float v2, int i2) {
-  if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+  const bool take = (v2 > v) | ((v2 == v) & (i2 < i));
+  v = take ? v2 : v;
+  i = take ? i2 : i;
 }
 
 // sum_kz P_kz w_8^kz / 512 (stage A of the autocorrelation at l_z = 1: the
@@ -92,7 +113,46 @@ static __device__ __forceinline__ float2 stageA(const float P[MZ]) {
   return f2(re * (1.0f / 512.0f), im * (1.0f / 512.0f));
 }
 
-constexpr size_t SMEM16 = sizeof(float2) * WAVES * SB_ELEMS + sizeof(float4) * 2 * NV1_MAX * 4;
+constexpr int LATQ_MAX = 64;      // rows of the lattice coefficient table
+constexpr int NC_IT = (NV1_MAX + 2) / 3;   // stage-C iterations per lane
+constexpr int ETAB = 8 * 17;        // spatial factors [kx 0..7][ky -8..8], zero outside the band
+constexpr size_t SMEM16 = sizeof(float2) * WAVES * SB_ELEMS + sizeof(float4) * 2 * NV1_MAX * 4 +
+                          sizeof(float2) * (LATQ_MAX * MZ + ETAB);
+
+// Hann along kx, power spectrum and stage A for one (plane kx, ky) column
+// of kz values.  The centre comes from registers (CREG) or from LDS; the
+// neighbours from LDS.  Plane -1 is the conjugate mirror of plane 1 and
+// plane 9 that of plane 7: S(-1, ky, kz) = conj S(1, -ky, -kz),
+// S(9, ky, kz) = conj S(7, -ky, -kz).  EDGE: 0 interior, 1 kx = 0, 2 kx = 8.
+template <int EDGE, bool CREG>
+static __device__ __forceinline__ float2 hann_x_power(const lds_v2* s_b, int ky, int kx, const float2 (&Hc)[MZ],
+                                                      float (&P)[MZ]) {
+#pragma unroll
+  for (int k = 0; k < MZ; k += 2) {
+    float4 l, rr, cc;
+    if (EDGE == 1) {
+      const float2 m0 = ld2(&s_b[sb_idx(1, (MY - ky) & 15, (MZ - k) & 7)]);
+      const float2 m1 = ld2(&s_b[sb_idx(1, (MY - ky) & 15, (MZ - k - 1) & 7)]);
+      l = make_float4(m0.x, -m0.y, m1.x, -m1.y);
+    } else {
+      l = ld4(&s_b[sb_idx(kx - 1, ky, k)]);
+    }
+    if (EDGE == 2) {
+      const float2 m0 = ld2(&s_b[sb_idx(7, (MY - ky) & 15, (MZ - k) & 7)]);
+      const float2 m1 = ld2(&s_b[sb_idx(7, (MY - ky) & 15, (MZ - k - 1) & 7)]);
+      rr = make_float4(m0.x, -m0.y, m1.x, -m1.y);
+    } else {
+      rr = ld4(&s_b[sb_idx(kx + 1, ky, k)]);
+    }
+    if (CREG) cc = make_float4(Hc[k].x, Hc[k].y, Hc[k + 1].x, Hc[k + 1].y);
+    else cc = ld4(&s_b[sb_idx(kx, ky, k)]);
+    const float h0x = 2.f * cc.x - l.x - rr.x, h0y = 2.f * cc.y - l.y - rr.y;
+    const float h1x = 2.f * cc.z - l.z - rr.z, h1y = 2.f * cc.w - l.w - rr.w;
+    P[k] = h0x * h0x + h0y * h0y;
+    P[k + 1] = h1x * h1x + h1y * h1y;
+  }
+  return stageA(P);
+}
 
 // One work tile: 4 adjacent anchor columns starting at 4*xb (one per
 // wavefront), rows [yb*TY, yb*TY + TY).  All 256 threads must call it.
@@ -107,20 +167,30 @@ static __device__ __forceinline__ unsigned short to_bf16(float f) {
 // the fallback; the background estimate is made later by finish16).
 template <int MODE>
 static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
-  float2* s_all = reinterpret_cast<float2*>(smem);
-  float4* s_tab = reinterpret_cast<float4*>(smem + sizeof(float2) * WAVES * SB_ELEMS);  // tabB rows, then tabC rows
+  lds_v2* s_all = (lds_v2*)(smem);
+  lds_v4* s_tab = (lds_v4*)(smem + sizeof(float2) * WAVES * SB_ELEMS);  // tabB rows, then tabC rows
+  lds_v2* s_g = (lds_v2*)(smem + sizeof(float2) * WAVES * SB_ELEMS + sizeof(float4) * 2 * NV1_MAX * 4);
   const int lane = threadIdx.x & 63;
   // wave-uniform values live in scalar registers
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  float2* s_b = s_all + wv * SB_ELEMS;
-  float2* s_q = s_b;                       // [9][16] after Hann along kx
-  float2* s_t = s_b + NXH * MY;            // [9][NV1_MAX]
+  lds_v2* s_b = s_all + wv * SB_ELEMS;
+  lds_v2* s_q = s_b;                       // [9][16] after Hann along kx
+  lds_v2* s_t = s_b + NXH * MY;            // [9][NV1_MAX]
   const int nvx = a.nvx, nvy = a.nvy, nv = a.nv;
   {
     const float4* tb = reinterpret_cast<const float4*>(a.tabB);
     const float4* tc = reinterpret_cast<const float4*>(a.tabC);
-    for (int i = threadIdx.x; i < 4 * nvy; i += 256) s_tab[i] = tb[i];
-    for (int i = threadIdx.x; i < 4 * nvx; i += 256) s_tab[4 * NV1_MAX + i] = tc[i];
+    for (int i = threadIdx.x; i < 4 * nvy; i += 256) s_tab[i] = v4f{tb[i].x, tb[i].y, tb[i].z, tb[i].w};
+    for (int i = threadIdx.x; i < 4 * nvx; i += 256) s_tab[4 * NV1_MAX + i] = v4f{tc[i].x, tc[i].y, tc[i].z, tc[i].w};
+    if (MODE != 2 && a.gtab != nullptr) {
+      for (int i = threadIdx.x; i < a.lat_q * MZ; i += 256) s_g[i] = v2f{a.gtab[i].x, a.gtab[i].y};
+      for (int i = threadIdx.x; i < ETAB; i += 256) {
+        const int p = i / 17, kc = i % 17 - 8;
+        float2 e = f2(0.f, 0.f);
+        if (p <= a.bx && kc >= -a.by && kc <= a.by) e = a.etab[p * (2 * a.by + 1) + kc + a.by];
+        s_g[LATQ_MAX * MZ + i] = v2f{e.x, e.y};
+      }
+    }
   }
   __syncthreads();                         // the only workgroup barrier
 
@@ -138,6 +208,9 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
   const int hC = lane / nvx, ixC = lane % nvx;
   const bool actC = lane < 3 * nvx;
   const float2 wy = a.twy[ky];
+  const int kyc = (ky <= 8) ? ky : ky - 16;
+  // lattice background coefficients (table and spatial factors in LDS)
+  const bool lattice = (MODE != 2) && (a.gtab != nullptr);
 
   const size_t HW = (size_t)a.H * a.W;
   const float2* rsA = a.rs + (size_t)pA * HW + x;
@@ -223,30 +296,45 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       const float2 dB = dpp2<ROR1>(HB[k]), uB = dpp2<ROR15>(HB[k]);
       HB[k] = f2(2.f * HB[k].x - dB.x - uB.x, 2.f * HB[k].y - dB.y - uB.y);
     }
-    // ---- unpack plane 0: S(0) = (C + conj C(-k)) / 2, S(8) = (C - conj C(-k)) / 2j;
-    // stage the y,z-windowed planes in LDS
+    // ---- stage the y,z-windowed planes in LDS, then unpack plane 0:
+    // S(0) = (C + conj C(-k)) / 2, S(8) = (C - conj C(-k)) / 2j
     wave_lds_sync();                     // previous row's stage C reads are done
-    {
-      float2 M[MZ];
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) M[k] = row_neg(HA[k]);
-      if (r == 0) {
-#pragma unroll
-        for (int k = 0; k < MZ; k += 2) {
-          const float2 u0 = HA[k], w0 = M[(MZ - k) & 7], u1 = HA[k + 1], w1 = M[(MZ - k - 1) & 7];
-          *reinterpret_cast<float4*>(&s_b[sb_idx(8, ky, k)]) =
-              make_float4(0.5f * (u0.y + w0.y), -0.5f * (u0.x - w0.x), 0.5f * (u1.y + w1.y), -0.5f * (u1.x - w1.x));
-          HA[k] = f2(0.5f * (u0.x + w0.x), 0.5f * (u0.y - w0.y));
-          HA[k + 1] = f2(0.5f * (u1.x + w1.x), 0.5f * (u1.y - w1.y));
-        }
-      }
-    }
 #pragma unroll
     for (int k = 0; k < MZ; k += 2) {
-      *reinterpret_cast<float4*>(&s_b[sb_idx(pA, ky, k)]) = make_float4(HA[k].x, HA[k].y, HA[k + 1].x, HA[k + 1].y);
-      *reinterpret_cast<float4*>(&s_b[sb_idx(pB, ky, k)]) = make_float4(HB[k].x, HB[k].y, HB[k + 1].x, HB[k + 1].y);
+      st4(&s_b[sb_idx(pA, ky, k)], HA[k].x, HA[k].y, HA[k + 1].x, HA[k + 1].y);
+      st4(&s_b[sb_idx(pB, ky, k)], HB[k].x, HB[k].y, HB[k + 1].x, HB[k + 1].y);
     }
     wave_lds_sync();
+    if (r == 0) {
+      // every read of plane 0 precedes every write to it (one wavefront,
+      // program order)
+      float2 w[MZ];
+#pragma unroll
+      for (int k = 0; k < MZ; ++k) w[k] = ld2(&s_b[sb_idx(0, (MY - ky) & 15, (MZ - k) & 7)]);
+#pragma unroll
+      for (int k = 0; k < MZ; k += 2) {
+        const float2 u0 = HA[k], u1 = HA[k + 1], w0 = w[k], w1 = w[k + 1];
+        st4(&s_b[sb_idx(8, ky, k)], 0.5f * (u0.y + w0.y), -0.5f * (u0.x - w0.x), 0.5f * (u1.y + w1.y),
+            -0.5f * (u1.x - w1.x));
+        st4(&s_b[sb_idx(0, ky, k)], 0.5f * (u0.x + w0.x), 0.5f * (u0.y - w0.y), 0.5f * (u1.x + w1.x),
+            0.5f * (u1.y - w1.y));
+      }
+    }
+    wave_lds_sync();
+    // issued here so that their latency overlaps the rest of the flow: this
+    // row's smoothed autocorrelation (stage-C lane (hC, ixC) owns the
+    // candidates iy = hC + 3j; rows past the grid read the last one) and the
+    // delayed input sample
+    float rprev[NC_IT];
+    float idel = 0.f;
+    if (MODE != 2) {
+      const float* rp = a.rsm + pix * nv;
+      const int off0 = hC * nvx + ixC, offl = (nvy - 1) * nvx + ixC;
+#pragma unroll
+      for (int j = 0; j < NC_IT; ++j) rprev[j] = rp[(unsigned)min(off0 + 3 * j * nvx, offl)];
+      const int xs = x - a.dx, ys = y - a.dy;
+      if (ring_delayed != nullptr && xs >= 0 && ys >= 0) idel = ring_delayed[(size_t)ys * a.W + xs];
+    }
 
     // ---- Hann along kx, power spectrum, stage A: Q(kx, ky) = sum_kz P w_z^kz.
     // Planes -1 and 9 are the conjugate mirrors of planes 1 and 7:
@@ -255,42 +343,13 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     float PA[MZ], PB[MZ], P8[MZ];
 #pragma unroll
     for (int k = 0; k < MZ; ++k) P8[k] = 0.f;
-    {
-      auto hxq = [&](const float2* Hc, int kx, float* P) -> float2 {
-#pragma unroll
-        for (int k = 0; k < MZ; k += 2) {
-          float4 l, rr, cc;
-          if (kx == 0) {
-            const float2 m0 = s_b[sb_idx(1, (MY - ky) & 15, (MZ - k) & 7)];
-            const float2 m1 = s_b[sb_idx(1, (MY - ky) & 15, (MZ - k - 1) & 7)];
-            l = make_float4(m0.x, -m0.y, m1.x, -m1.y);
-          } else {
-            l = *reinterpret_cast<const float4*>(&s_b[sb_idx(kx - 1, ky, k)]);
-          }
-          if (kx == 8) {
-            const float2 m0 = s_b[sb_idx(7, (MY - ky) & 15, (MZ - k) & 7)];
-            const float2 m1 = s_b[sb_idx(7, (MY - ky) & 15, (MZ - k - 1) & 7)];
-            rr = make_float4(m0.x, -m0.y, m1.x, -m1.y);
-          } else {
-            rr = *reinterpret_cast<const float4*>(&s_b[sb_idx(kx + 1, ky, k)]);
-          }
-          if (Hc) cc = make_float4(Hc[k].x, Hc[k].y, Hc[k + 1].x, Hc[k + 1].y);
-          else cc = *reinterpret_cast<const float4*>(&s_b[sb_idx(kx, ky, k)]);
-          const float h0x = 2.f * cc.x - l.x - rr.x, h0y = 2.f * cc.y - l.y - rr.y;
-          const float h1x = 2.f * cc.z - l.z - rr.z, h1y = 2.f * cc.w - l.w - rr.w;
-          P[k] = h0x * h0x + h0y * h0y;
-          P[k + 1] = h1x * h1x + h1y * h1y;
-        }
-        return stageA(P);
-      };
-      if (r == 0) {
-        QA = hxq(HA, 0, PA);
-        Q8 = hxq(nullptr, 8, P8);
-      } else {
-        QA = hxq(HA, pA, PA);
-      }
-      QB = hxq(HB, pB, PB);
+    if (r == 0) {
+      QA = hann_x_power<1, false>(s_b, ky, 0, HA, PA);
+      Q8 = hann_x_power<2, false>(s_b, ky, 8, HA, P8);
+    } else {
+      QA = hann_x_power<0, false>(s_b, ky, pA, HA, PA);
     }
+    QB = hann_x_power<0, false>(s_b, ky, pB, HB, PB);
     if (MODE >= 1) {
       // learned-model input: x = ln(P + eps) - mean over all Mx*My*Mz bins,
       // eps = 1e-6 max P; stored for kx = 0..8 ([kx][ky][kz], BF16); bins
@@ -336,7 +395,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
         if (ky == 0 || ky == 8) v = q;
         else if (ky < 8) v = f2(q.x + m.x, q.y + m.y);
         else v = f2(m.x - q.x, m.y - q.y);
-        s_q[kx * MY + ky] = v;
+        st2(&s_q[kx * MY + ky], v);
       };
       put(pA, QA, mA);
       put(pB, QB, mB);
@@ -348,7 +407,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     if (actB) {
       float cB[7], sB[7], c8B;
       {
-        const float* tb = reinterpret_cast<const float*>(s_tab) + iyB * 16;
+        const lds_float* tb = (const lds_float*)(s_tab) + iyB * 16;
 #pragma unroll
         for (int k = 0; k < 7; ++k) { cB[k] = tb[k]; sB[k] = tb[7 + k]; }
         c8B = tb[14];
@@ -356,18 +415,35 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
 #pragma unroll 1
       for (int j = 0; j < 3; ++j) {
         const int kx = 3 * gB + j;
-        const float2* q = s_q + kx * MY;
+        const lds_v2* q = s_q + kx * MY;
         float tx = q[0].x + c8B * q[8].x, ty = q[0].y + c8B * q[8].y;
 #pragma unroll
         for (int k = 1; k < 8; ++k) {
-          const float2 A = q[k], Bv = q[16 - k];
+          const v2f A = q[k], Bv = q[16 - k];
           tx += cB[k - 1] * A.x - sB[k - 1] * Bv.y;
           ty += cB[k - 1] * A.y + sB[k - 1] * Bv.x;
         }
-        s_t[kx * NV1_MAX + iyB] = f2(tx, ty);
+        st2(&s_t[kx * NV1_MAX + iyB], f2(tx, ty));
       }
     }
     wave_lds_sync();
+
+    // The background estimate needs this row's posterior state again: read
+    // it back (it was written above and is still in L2) rather than keep 32
+    // registers live through the flow stages; issued before stage C so the
+    // latency overlaps it.  The empty asm hides the address from the
+    // compiler, which would otherwise forward the stored registers.
+    if (MODE != 2) {
+      unsigned long long addr = (unsigned long long)(a.st + pix * NCOL * MZ);
+      asm volatile("" : "+s"(addr));
+      const RMDF_GLOBAL v2f* src = (const RMDF_GLOBAL v2f*)addr;
+#pragma unroll
+      for (int k = 0; k < MZ; ++k) {
+        const v2f u = src[(pA * MY + ky) * MZ + k], v = src[(pB * MY + ky) * MZ + k];
+        XA[k] = f2(u.x, u.y);
+        XB[k] = f2(v.x, v.y);
+      }
+    }
 
     // ---- stage C: R = T0 + T8 cos(pi l_x) + sum_kx 2 Re[T e^{+j phi}],
     // smoothing and argmax
@@ -376,26 +452,30 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     if (actC) {
       float cC[7], sC[7], c8C;
       {
-        const float* tc = reinterpret_cast<const float*>(s_tab) + (4 * NV1_MAX + 4 * ixC) * 4;
+        const lds_float* tc = (const lds_float*)(s_tab) + (4 * NV1_MAX + 4 * ixC) * 4;
 #pragma unroll
         for (int k = 0; k < 7; ++k) { cC[k] = tc[k]; sC[k] = tc[7 + k]; }
         c8C = tc[14];
       }
-      for (int iy = hC; iy < nvy; iy += 3) {
-        float rv = s_t[0 * NV1_MAX + iy].x + c8C * s_t[8 * NV1_MAX + iy].x;
 #pragma unroll
-        for (int kx = 1; kx < 8; ++kx) {
-          const float2 t = s_t[kx * NV1_MAX + iy];
-          rv += cC[kx - 1] * t.x - sC[kx - 1] * t.y;
+      for (int j = 0; j < NC_IT; ++j) {
+        const int iy = hC + 3 * j;
+        if (iy < nvy) {
+          float rv = s_t[0 * NV1_MAX + iy].x + c8C * s_t[8 * NV1_MAX + iy].x;
+#pragma unroll
+          for (int kx = 1; kx < 8; ++kx) {
+            const v2f t = s_t[kx * NV1_MAX + iy];
+            rv += cC[kx - 1] * t.x - sC[kx - 1] * t.y;
+          }
+          const int w = iy * nvx + ixC;
+          float sm = rv;                   // learned mode: instantaneous R (no smoother state)
+          if (MODE != 2) {
+            sm = (1.f - a.alpha) * rv + a.alpha * rprev[j];
+            a.rsm[pix * nv + w] = sm;
+          }
+          amax_merge(bv, bi, sm, w);
         }
-        const int w = iy * nvx + ixC;
-        float sm = rv;                     // learned mode: instantaneous R (no smoother state)
-        if (MODE != 2) {
-          float* rp = a.rsm + pix * nv + w;
-          sm = (1.f - a.alpha) * rv + a.alpha * (*rp);
-          *rp = sm;
-        }
-        amax_merge(bv, bi, sm, w);
+        __builtin_amdgcn_sched_barrier(0);   // keep one iteration's LDS reads in flight at a time
       }
     }
 #pragma unroll
@@ -411,29 +491,44 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     }
 
     // ---- background estimate with the chosen velocity's coefficients
-    const int hsel = (a.vmode == 2) ? nv : istar;
+    const int hsel = __builtin_amdgcn_readfirstlane((a.vmode == 2) ? nv : istar);
     float acc = 0.f;
-    {
-      const int kyc = (ky <= 8) ? ky : ky - 16;
-      if (kyc >= -a.by && kyc <= a.by) {
-        const size_t row = (size_t)hsel * (a.bx + 1);
-        if (pA <= a.bx) {
-          const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+    if (lattice) {
+      // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
+      const int nq = a.latq[hsel];
+      const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
+      const int qm = a.lat_q - 1;
+      const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
+      const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
+      float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
 #pragma unroll
-          for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
-        }
-        if (pB <= a.bx) {
-          const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+      for (int k = 0; k < MZ; k += 2) {
+        const float4 g = ld4(&gA[k]);
+        sA.x += g.x * XA[k].x - g.y * XA[k].y + g.z * XA[k + 1].x - g.w * XA[k + 1].y;
+        sA.y += g.x * XA[k].y + g.y * XA[k].x + g.z * XA[k + 1].y + g.w * XA[k + 1].x;
+        const float4 h = ld4(&gB[k]);
+        sB.x += h.x * XB[k].x - h.y * XB[k].y + h.z * XB[k + 1].x - h.w * XB[k + 1].y;
+        sB.y += h.x * XB[k].y + h.y * XB[k].x + h.z * XB[k + 1].y + h.w * XB[k + 1].x;
+      }
+      const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
+      const float2 EA = ld2(e), EB = ld2(e + 4 * 17);
+      acc = (EA.x * sA.x - EA.y * sA.y) + (EB.x * sB.x - EB.y * sB.y);
+    } else if (kyc >= -a.by && kyc <= a.by) {
+      const size_t row = (size_t)hsel * (a.bx + 1);
+      if (pA <= a.bx) {
+        const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-          for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
-        }
+        for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
+      }
+      if (pB <= a.bx) {
+        const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
       }
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (lane == 0) {
-      const int xs = x - a.dx, ys = y - a.dy;
-      float idel = (ring_delayed != nullptr && xs >= 0 && ys >= 0) ? ring_delayed[(size_t)ys * a.W + xs] : 0.f;
       if (!isfinite(idel)) idel = 0.f;
       a.out[pix] = idel - acc;
       if (a.vmode == 2) {

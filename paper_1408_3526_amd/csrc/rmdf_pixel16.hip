@@ -7,11 +7,20 @@
 namespace rmdf {
 namespace p16 {
 
+// Three workgroups (12 wavefronts) per CU fit the LDS; the register budget
+// is set to match (168 VGPRs).  The feature-writing search keeps more values
+// live and gets two.
 template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_pixel16(PixArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_pixel16(PixArgs a) {
   __shared__ __align__(16) char smem[SMEM16];
   const int xblocks = (a.W + WAVES - 1) / WAVES;
   pixel16_tile<MODE>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_pixel16_feat(PixArgs a) {
+  __shared__ __align__(16) char smem[SMEM16];
+  const int xblocks = (a.W + WAVES - 1) / WAVES;
+  pixel16_tile<1>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
 }
 
 __global__ void __launch_bounds__(256) k_finish16(PixArgs a, const float* vc, float thr) {
@@ -30,7 +39,7 @@ hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   const int xblocks = (a.W + p16::WAVES - 1) / p16::WAVES;
   const int yblocks = (a.H + a.TY - 1) / a.TY;
   if (mode == 0) hipLaunchKernelGGL(p16::k_pixel16<0>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
-  else if (mode == 1) hipLaunchKernelGGL(p16::k_pixel16<1>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else if (mode == 1) hipLaunchKernelGGL(p16::k_pixel16_feat, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else hipLaunchKernelGGL(p16::k_pixel16<2>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -57,14 +57,17 @@ def test_batch_graph_replays_equal_eager(tile):
 
 
 def _copy_to(ptr, src):
-    """Device-to-device copy of a torch tensor into a raw device address
-    (synchronous, after a device-wide synchronisation)."""
+    """Device-to-device copy of a torch tensor into a raw device address,
+    complete on return (device-wide synchronisation before and after)."""
     import ctypes
     hip = ctypes.CDLL("libamdhip64.so")
     hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
     torch.cuda.synchronize()
     rc = hip.hipMemcpy(ctypes.c_void_p(ptr), ctypes.c_void_p(src.data_ptr()), src.numel() * 4, 3)
     assert rc == 0
+    # a device-to-device hipMemcpy may return before the copy is done, and the
+    # batch runs on a stream that does not wait for the null stream
+    torch.cuda.synchronize()
 
 
 def test_batch_matches_oracle(orc):

@@ -47,7 +47,8 @@ def run_gpu(frames, M, gx, gy, spec_at=None, **kw):
         vxy.append(v.cpu().numpy())
         idx.append(i.cpu().numpy())
     res = {"out": np.stack(out), "idx": np.stack(idx), "vxy": np.stack(vxy),
-           "rs": f.smoothed_r().cpu().numpy(), "nonfinite": f.nonfinite_count()}
+           "rs": f.smoothed_r().cpu().numpy(), "nonfinite": f.nonfinite_count(),
+           "lattice": f.coeff_lattice()}
     if spec_at is not None:
         xs, ys = spec_at
         res["spec"] = f.spectrum(xs, ys).cpu().numpy()
@@ -149,6 +150,21 @@ def test_parity_window_16x16x8_flow(orc, variant):
     check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
 
 
+@pytest.mark.parametrize("lo,hi,step,q", [(-4, 4, 1.0, 16), (-2, 2, 0.25, 64), (-1.5, 1.5, 0.3, 0)])
+def test_parity_16x16x8_coefficient_storage(orc, lo, hi, step, q):
+    """Background coefficients from the lattice table (grid step 1, 1/4
+    px/frame: 16 and 64 rows) and from the per-candidate table (step 0.3 is
+    on no lattice) give the oracle's output."""
+    sc = scenes.flow_scene(11, H=30, W=29, T=11, n_targets=2, band_width=(6, 9))
+    g = scenes.grid(lo, hi, step)
+    M = (16, 16, 8)
+    gres = run_gpu(sc.frames, M, g, g, tile_rows=8, kernel_variant=2)
+    assert gres["lattice"] == q
+    r = orc.run(_cfg(orc, 30, 29, M, g, g), sc.frames, want_rs=True)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
+
+
 def test_parity_paper_configuration(orc):
     """The paper's parameters: 9x9x5 window (K = 4, 4, 2), B = 3, m' = K,
     17x17 grid at 0.25 px/frame, on the paper's simulated scene."""
@@ -164,6 +180,7 @@ def test_parity_paper_configuration(orc):
 
 
 @pytest.mark.parametrize("M,B,v", [((8, 8, 4), 3, (0.7, -1.3)), ((16, 16, 8), 6, (-2.3, 0.45)),
+                                   ((16, 16, 8), 5, (1.5, -0.75)),
                                    ((9, 9, 5), 3, (1.625, 0.625))])
 def test_fixed_velocity_pef_null(orc, M, B, v):
     """Band-limited clutter translating at v is removed (fixed-velocity mode)."""
