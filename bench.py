@@ -83,13 +83,124 @@ def copy_calibration(nbytes=1 << 30, reps=10):
                       "launches": reps}), flush=True)
 
 
-def make_frames(wl):
+# Batched streams: (count, H, W, window, velocity grid (lo, hi, step), targets)
+BATCH24 = [(8, 256, 320, (8, 8, 4), (-4.0, 4.0, 1.0), 5),
+           (8, 512, 640, (16, 16, 8), (-4.0, 4.0, 0.5), 20),
+           (8, 1024, 1280, (16, 16, 8), (-4.0, 4.0, 0.5), 50)]
+
+
+def batch_bench(args):
+    """24 streams of three sizes advanced together, one hipGraph launch per
+    step (frames copied into the streams' input slots inside the timed
+    region); tiles chosen by the autotuner first.  Prints one JSON line."""
+    import torch
+
+    from paper_1408_3526_amd import binding, scenes
+    torch.cuda.set_device(0)
+    specs, frames = [], []
+    seed = 300
+    nfr = args.frames or 12
+    t0 = time.perf_counter()
+    for count, H, W, M, gr, nt in BATCH24:
+        g = scenes.grid(*gr)
+        for _ in range(count):
+            seed += 1
+            fr = scenes.flow_scene(seed, H=H, W=W, T=nfr, n_targets=nt, varying_noise=(H >= 1024)).frames
+            frames.append(torch.from_numpy(fr).cuda())
+            specs.append(dict(H=H, W=W, M=M, gx=g, gy=g))
+        print("generated %d streams of %dx%d (%.0f s)" % (count, W, H, time.perf_counter() - t0), file=sys.stderr,
+              flush=True)
+    b = binding.Batch(specs)
+    for i in range(args.warmup):
+        b.push([f[i % nfr] for f in frames])
+    report = b.autotune(iters=5)
+    print(report, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    b.set_timing(True)
+    w0 = time.perf_counter()
+    for i in range(args.steps):
+        b.push([f[(args.warmup + i) % nfr] for f in frames])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    lat = b.latency()
+    b.close()
+    px = sum(sp["H"] * sp["W"] for sp in specs)
+    byt = sum(sp["H"] * sp["W"] * algorithmic_bytes_per_pixel_frame(sp["M"], len(sp["gx"]) ** 2) for sp in specs)
+    res = {"metric": "batched streams: aggregate pixel-frames/s, per-step latency", "mode": "batch24",
+           "value": args.steps * px / wall, "unit": "pixel-frames/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "24 streams: 8 x 320x256 (8x8x4, 9x9 grid), 8 x 640x512 and 8 x 1280x1024 "
+                                  "(16x16x8, 17x17 grid at 0.5 px/frame)", "frames_distinct": nfr,
+                      "pixels_per_step": px},
+           "latency_ms": {"p50": lat["p50_ms"], "p99": lat["p99_ms"], "mean": lat["mean_ms"]},
+           "algorithmic_GBps": byt * args.steps / wall / 1e9,
+           "hbm_frac": byt * args.steps / wall / 1e9 / HBM_PEAK_GBS,
+           "autotune": report.strip().splitlines()}
+    print(json.dumps(res), flush=True)
+
+
+def make_scene(wl):
     from paper_1408_3526_amd import scenes
     H, W = wl["H"], wl["W"]
     if wl["M"] == (8, 8, 4):
-        return scenes.translate_scene(wl["seed"], H=H, W=W, T=wl["frames"], v=(1, -2), n_targets=wl["targets"]).frames
+        return scenes.translate_scene(wl["seed"], H=H, W=W, T=wl["frames"], v=(1, -2), n_targets=wl["targets"])
     return scenes.flow_scene(wl["seed"], H=H, W=W, T=wl["frames"], n_targets=wl["targets"],
-                             varying_noise=(H >= 1024)).frames
+                             varying_noise=(H >= 1024))
+
+
+def learned_leg(dev, sc, M, g, steps, warmup):
+    """Learned velocity mode (trained weights shipped with the package) on the
+    same frames: pixel-frames/s, and the PEF residual RMS of both modes over
+    the last 10 of the first 40 frames (pixels away from the targets and the
+    frame border).  None when no weights are present."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3526_amd import binding, learned
+    if M != (16, 16, 8) or not os.path.exists(learned.DEFAULT_WEIGHTS):
+        return None
+    w = np.load(learned.DEFAULT_WEIGHTS)
+    T, H, W = dev.shape
+
+    def make(mode):
+        if mode == "learned":
+            f = binding.Filter(H, W, *M, g, g, velocity_mode=binding.VEL_LEARNED, conf_threshold=0.9)
+            f.set_weights(w)
+        else:
+            f = binding.Filter(H, W, *M, g, g)
+        return f
+
+    resid = {}
+    n_eval = min(40, T)
+    for mode in ("plain", "learned"):
+        f = make(mode)
+        r = []
+        for t in range(n_eval):
+            f.push_frame(dev[t])
+            if t >= n_eval - 10:
+                out = f.output().cpu().numpy()
+                r.append(learned.residual_rms(out, sc.targets, t - M[2] // 2))
+        f.close()
+        resid[mode] = float(np.mean(r))
+    f = make("learned")
+    for i in range(warmup):
+        f.push_frame(dev[i % T])
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(steps):
+        f.push_frame(dev[(warmup + i) % T])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    f.close()
+    return {"value": steps * H * W / (ms / 1e3), "unit": "pixel-frames/s", "ms_per_step": ms / steps,
+            "residual_rms": resid["learned"], "plain_residual_rms": resid["plain"],
+            "residual_ratio": resid["learned"] / resid["plain"],
+            "equal_residual_within_5pct": bool(resid["learned"] <= 1.05 * resid["plain"]),
+            "conf_threshold": 0.9}
 
 
 def cpu_baseline(frames, wl, g, budget_frames=8, crop=64):
@@ -120,6 +231,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 generic, 2 wave-per-anchor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch24", action="store_true",
+                    help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (the reference kernel for the PMC byte counters)")
     args = ap.parse_args()
@@ -129,6 +242,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.batch24:
+        batch_bench(args)
         return
 
     import numpy as np
@@ -143,7 +259,8 @@ def main():
     g = scenes.grid(*wl["grid"])
     nv = len(g) ** 2
     t0 = time.perf_counter()
-    frames = make_frames(wl)
+    sc = make_scene(wl)
+    frames = sc.frames
     print("generated %d frames in %.1f s" % (frames.shape[0], time.perf_counter() - t0), file=sys.stderr, flush=True)
 
     torch.cuda.set_device(0)
@@ -204,6 +321,10 @@ def main():
         "kernel_ms": {"pixel": pix_ms, "row": kms[1][0] / max(kms[1][1], 1), "ingest": kms[2][0] / max(kms[2][1], 1)},
         "wall_s": wall,
     }
+    lr = learned_leg(dev, sc, M, g, min(args.steps, 200), args.warmup)
+    if lr is not None:
+        lr["vs_plain"] = lr["value"] / value
+        res["learned"] = lr
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(frames, wl, g)
     print(json.dumps(res), flush=True)

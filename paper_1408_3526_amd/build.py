@@ -16,7 +16,10 @@ CSRC = os.path.join(HERE, "csrc")
 SO = os.path.join(HERE, "librmdf.so")
 ARCH = os.environ.get("RMDF_OFFLOAD_ARCH", "gfx950")
 
-HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
+# -ffp-contract=on: a*b+c is fused only within one source expression, so a
+# device function computes the same bits in every kernel it is inlined into
+# (the batched and single-stream kernels share the per-pixel tiles).
+HIP_FLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC", "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 

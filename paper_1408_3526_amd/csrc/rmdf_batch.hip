@@ -78,7 +78,8 @@ static __device__ void item_loop(const BatchPixDesc* __restrict__ d, const int4*
   for (;;) {
     if (threadIdx.x == 0) *s_item = atomicAdd(queue, 1u);
     __syncthreads();
-    const unsigned int it = *s_item;
+    // uniform: the item's descriptor then lives in scalar registers
+    const unsigned int it = __builtin_amdgcn_readfirstlane(*s_item);
     __syncthreads();                    // all have read s_item before it is overwritten
     if (it >= (unsigned int)n_items) break;
     const int4 w = items[it];
@@ -95,11 +96,12 @@ template <> struct KindSmem<KIND_995> { static constexpr size_t v = Shape<9, 9, 
 template <> struct KindSmem<KIND_16G> { static constexpr size_t v = Shape<16, 16, 8>::SMEM; };
 template <> struct KindSmem<KIND_16W> { static constexpr size_t v = p16::SMEM16; };
 
-// One persistent kernel per tile family (its queue is queue[KIND]); the
-// 16x16x8 wave-per-anchor tile gets the register budget of three resident
-// workgroups per CU, as in the single-stream kernel.
+// One persistent kernel per tile family (its queue is queue[KIND]).  The
+// 16x16x8 wave-per-anchor tile needs more registers here than in the
+// single-stream kernel (the per-item descriptor and queue state stay live), so
+// it runs two workgroups per CU instead of spilling.
 template <int KIND>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIND_16W ? 3 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIND_16W ? 2 : 1)))
 k_batch_tiles(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items, BatchState bs) {
   __shared__ __align__(16) char smem[KindSmem<KIND>::v];
   __shared__ unsigned int s_item;

@@ -534,7 +534,7 @@ rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, f
   if ((e = hipMemcpyAsync(c->xy_scratch, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return hip_fail(c, e, "anchor upload");
   e = rmdf::launch_spectrum(c->MX, c->MY, c->MZ, c->st, c->W, c->xy_scratch, npix, reinterpret_cast<float2*>(spec),
-                            c->stream);
+                            c->variant == 2, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "spectrum launch");
   // the host array must outlive the copy
   e = hipStreamSynchronize(c->stream);

@@ -19,7 +19,8 @@ struct PixArgs {
   float alpha, inv_sqrt_my;
   float fvx, fvy;
   const float2* rs;            // row spectra [planes][H][W]
-  float2* st;                  // observer state [H][W][planes*My][Mz]
+  float2* st;                  // observer state [H][W][planes*My][Mz] (16x16x8 wave-per-anchor
+                               // kernel: [H][W][Mz/2][planes*My][2])
   float* rsm;                  // smoothed autocorrelation [H][W][nv]
   const float* ring_delayed;   // input frame t - m'_t, or nullptr while t < m'_t
   float* out;                  // [H][W]
@@ -52,8 +53,9 @@ bool shape_supported(int mx, int my, int mz);
 int planes_for(int mx);
 hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s);
 hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s);
+// layout16: the state is in the wave-per-anchor 16x16x8 layout
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
-                           hipStream_t s);
+                           bool layout16, hipStream_t s);
 bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, hipStream_t s);

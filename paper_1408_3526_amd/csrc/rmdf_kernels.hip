@@ -63,11 +63,16 @@ __global__ void __launch_bounds__(256) k_pixel(PixArgs a) {
 // ---------------------------------------------------------------------------
 // Full spectrum S(k; n) = sqrt(Mz) * X at chosen anchors, unpacked to
 // [npix][Mx][My][Mz] interleaved complex.
-template <int MX, int MY, int MZ>
+// IL: the wave-per-anchor 16x16x8 state layout [kz / 2][plane][ky] x (kz even,
+// kz odd); otherwise [plane][ky][kz].
+template <int MX, int MY, int MZ, bool IL>
 __global__ void k_spectrum(const float2* __restrict__ st, int W, const int* __restrict__ xy, int npix,
                            float2* __restrict__ out) {
   using SH = Shape<MX, MY, MZ>;
   constexpr int N = MX * MY * MZ;
+  auto at = [](int p, int ky, int kz) {
+    return IL ? ((kz >> 1) * SH::NCOL + p * MY + ky) * 2 + (kz & 1) : (p * MY + ky) * MZ + kz;
+  };
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= npix * N) return;
   const int ip = gid / N, b = gid % N;
@@ -78,15 +83,15 @@ __global__ void k_spectrum(const float2* __restrict__ st, int W, const int* __re
   if (2 * kx > MX) { kx = MX - kx; kyy = (MY - kyy) % MY; kz = (MZ - kz) % MZ; cj = true; }
   float2 r;
   if (kx == 0 || (SH::EVEN && 2 * kx == MX)) {
-    const float2 u = X[kyy * MZ + kz];
+    const float2 u = X[at(0, kyy, kz)];
     if (!SH::EVEN) r = u;
     else {
-      const float2 w = X[((MY - kyy) % MY) * MZ + (MZ - kz) % MZ];
+      const float2 w = X[at(0, (MY - kyy) % MY, (MZ - kz) % MZ)];
       if (kx == 0) r = make_float2(0.5f * (u.x + w.x), 0.5f * (u.y - w.y));
       else         r = make_float2(0.5f * (u.y + w.y), -0.5f * (u.x - w.x));
     }
   } else {
-    r = X[(kx * MY + kyy) * MZ + kz];
+    r = X[at(kx, kyy, kz)];
   }
   if (cj) r = cconj(r);
   out[gid] = cscale(r, sqrtf((float)MZ));
@@ -110,10 +115,10 @@ static hipError_t launch_row_t(const float* f, float2* rs, const float2* twx, in
   return hipGetLastError();
 }
 
-template <int MX, int MY, int MZ>
+template <int MX, int MY, int MZ, bool IL = false>
 static hipError_t launch_spec_t(const float2* st, int W, const int* xy, int npix, float2* out, hipStream_t s) {
   const int n = npix * MX * MY * MZ;
-  hipLaunchKernelGGL((k_spectrum<MX, MY, MZ>), dim3((n + 255) / 256), dim3(256), 0, s, st, W, xy, npix, out);
+  hipLaunchKernelGGL((k_spectrum<MX, MY, MZ, IL>), dim3((n + 255) / 256), dim3(256), 0, s, st, W, xy, npix, out);
   return hipGetLastError();
 }
 
@@ -138,9 +143,11 @@ hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int
 }
 
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
-                           hipStream_t s) {
+                           bool layout16, hipStream_t s) {
   if (mx == 8 && my == 8 && mz == 4) return launch_spec_t<8, 8, 4>(st, W, xy, npix, out, s);
-  if (mx == 16 && my == 16 && mz == 8) return launch_spec_t<16, 16, 8>(st, W, xy, npix, out, s);
+  if (mx == 16 && my == 16 && mz == 8)
+    return layout16 ? launch_spec_t<16, 16, 8, true>(st, W, xy, npix, out, s)
+                    : launch_spec_t<16, 16, 8>(st, W, xy, npix, out, s);
   if (mx == 9 && my == 9 && mz == 5) return launch_spec_t<9, 9, 5>(st, W, xy, npix, out, s);
   return hipErrorInvalidValue;
 }

@@ -80,6 +80,13 @@ static __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Observer state of the 16x16x8 kernel, per pixel: [kz / 2][plane][ky] x
+// (kz even, kz odd) complex, so that one 16-byte load per lane covers 1 KB
+// of contiguous memory across the wavefront.  Float2 index of (plane, ky, kz):
+static __host__ __device__ __forceinline__ int st16_index(int p, int ky, int kz) {
+  return ((kz >> 1) * NCOL + p * MY + ky) * 2 + (kz & 1);
+}
+
 // s_b index of (plane kx in [0, 8], ky, kz)
 static __device__ __forceinline__ int sb_idx(int kx, int ky, int kz) { return (kx * MY + ky) * SB_KZ + kz; }
 
@@ -227,13 +234,19 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
 
   for (int y = y0; y < y1; ++y) {
     const size_t pix = (size_t)y * a.W + x;
-    // observer state of this anchor (latency is hidden by the other resident
-    // wavefronts; a register prefetch would halve the occupancy)
+    // observer state of this anchor: one 1 KB contiguous run per instruction
+    // (state layout [kz pair][plane][ky] x 2 complex, see st16_index)
     float2 XA[MZ], XB[MZ];
     {
-      const float2* src = a.st + pix * NCOL * MZ;
+      const float4* src = reinterpret_cast<const float4*>(a.st + pix * NCOL * MZ);
 #pragma unroll
-      for (int k = 0; k < MZ; ++k) { XA[k] = src[(pA * MY + ky) * MZ + k]; XB[k] = src[(pB * MY + ky) * MZ + k]; }
+      for (int j = 0; j < MZ / 2; ++j) {
+        const float4 u = src[j * NCOL + pA * MY + ky], v = src[j * NCOL + pB * MY + ky];
+        XA[2 * j] = f2(u.x, u.y);
+        XA[2 * j + 1] = f2(u.z, u.w);
+        XB[2 * j] = f2(v.x, v.y);
+        XB[2 * j + 1] = f2(v.z, v.w);
+      }
     }
     // ---- column sliding DFT
     {
@@ -264,9 +277,12 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
         XA[k] = f2(XA[k].x + eA.x, XA[k].y + eA.y);
         XB[k] = f2(XB[k].x + eB.x, XB[k].y + eB.y);
       }
-      float2* dst = a.st + pix * NCOL * MZ;
+      float4* dst = reinterpret_cast<float4*>(a.st + pix * NCOL * MZ);
 #pragma unroll
-      for (int k = 0; k < MZ; ++k) { dst[(pA * MY + ky) * MZ + k] = XA[k]; dst[(pB * MY + ky) * MZ + k] = XB[k]; }
+      for (int j = 0; j < MZ / 2; ++j) {
+        dst[j * NCOL + pA * MY + ky] = make_float4(XA[2 * j].x, XA[2 * j].y, XA[2 * j + 1].x, XA[2 * j + 1].y);
+        dst[j * NCOL + pB * MY + ky] = make_float4(XB[2 * j].x, XB[2 * j].y, XB[2 * j + 1].x, XB[2 * j + 1].y);
+      }
     }
     // ---- high-pass + Hann along kz (2X(k) - X(k-1) - X(k+1); the 1/4 per
     // axis is folded into the stage-A weights)
@@ -428,23 +444,6 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     }
     wave_lds_sync();
 
-    // The background estimate needs this row's posterior state again: read
-    // it back (it was written above and is still in L2) rather than keep 32
-    // registers live through the flow stages; issued before stage C so the
-    // latency overlaps it.  The empty asm hides the address from the
-    // compiler, which would otherwise forward the stored registers.
-    if (MODE != 2) {
-      unsigned long long addr = (unsigned long long)(a.st + pix * NCOL * MZ);
-      asm volatile("" : "+s"(addr));
-      const RMDF_GLOBAL v2f* src = (const RMDF_GLOBAL v2f*)addr;
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const v2f u = src[(pA * MY + ky) * MZ + k], v = src[(pB * MY + ky) * MZ + k];
-        XA[k] = f2(u.x, u.y);
-        XB[k] = f2(v.x, v.y);
-      }
-    }
-
     // ---- stage C: R = T0 + T8 cos(pi l_x) + sum_kx 2 Re[T e^{+j phi}],
     // smoothing and argmax
     float bv = -INFINITY;
@@ -490,40 +489,62 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       continue;
     }
 
-    // ---- background estimate with the chosen velocity's coefficients
+    // ---- background estimate with the chosen velocity's coefficients.  It
+    // needs this row's posterior state again: it is read back (written above,
+    // still in L2) one plane at a time rather than kept in 32 registers
+    // through the flow stages.  The empty asm hides the address from the
+    // compiler, which would otherwise forward the stored registers.
     const int hsel = __builtin_amdgcn_readfirstlane((a.vmode == 2) ? nv : istar);
     float acc = 0.f;
-    if (lattice) {
-      // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
-      const int nq = a.latq[hsel];
-      const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
-      const int qm = a.lat_q - 1;
-      const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
-      const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
-      float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
+    {
+      unsigned long long addr = (unsigned long long)(a.st + pix * NCOL * MZ);
+      asm volatile("" : "+s"(addr));
+      // element kz of column (p, ky) is float2 (kz/2 * 128 + p * 16 + ky) * 2 + kz % 2
+      const RMDF_GLOBAL v2f* xA = (const RMDF_GLOBAL v2f*)addr + 2 * (pA * MY + ky);
+      const RMDF_GLOBAL v2f* xB = (const RMDF_GLOBAL v2f*)addr + 2 * (pB * MY + ky);
+      if (lattice) {
+        // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
+        const int nq = a.latq[hsel];
+        const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
+        const int qm = a.lat_q - 1;
+        const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
+        const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
+        const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
+        float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
 #pragma unroll
-      for (int k = 0; k < MZ; k += 2) {
-        const float4 g = ld4(&gA[k]);
-        sA.x += g.x * XA[k].x - g.y * XA[k].y + g.z * XA[k + 1].x - g.w * XA[k + 1].y;
-        sA.y += g.x * XA[k].y + g.y * XA[k].x + g.z * XA[k + 1].y + g.w * XA[k + 1].x;
-        const float4 h = ld4(&gB[k]);
-        sB.x += h.x * XB[k].x - h.y * XB[k].y + h.z * XB[k + 1].x - h.w * XB[k + 1].y;
-        sB.y += h.x * XB[k].y + h.y * XB[k].x + h.z * XB[k + 1].y + h.w * XB[k + 1].x;
-      }
-      const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
-      const float2 EA = ld2(e), EB = ld2(e + 4 * 17);
-      acc = (EA.x * sA.x - EA.y * sA.y) + (EB.x * sB.x - EB.y * sB.y);
-    } else if (kyc >= -a.by && kyc <= a.by) {
-      const size_t row = (size_t)hsel * (a.bx + 1);
-      if (pA <= a.bx) {
-        const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+        for (int k = 0; k < MZ; ++k) {
+          const v2f u = xA[(k >> 1) * 2 * NCOL + (k & 1)], g = gA[k];
+          sA.x += g.x * u.x - g.y * u.y;
+          sA.y += g.x * u.y + g.y * u.x;
+        }
+        const float2 EA = ld2(e);
+        acc = EA.x * sA.x - EA.y * sA.y;
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
-      }
-      if (pB <= a.bx) {
-        const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+        for (int k = 0; k < MZ; ++k) {
+          const v2f u = xB[(k >> 1) * 2 * NCOL + (k & 1)], g = gB[k];
+          sB.x += g.x * u.x - g.y * u.y;
+          sB.y += g.x * u.y + g.y * u.x;
+        }
+        const float2 EB = ld2(e + 4 * 17);
+        acc += EB.x * sB.x - EB.y * sB.y;
+      } else if (kyc >= -a.by && kyc <= a.by) {
+        const size_t row = (size_t)hsel * (a.bx + 1);
+        if (pA <= a.bx) {
+          const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
+          for (int k = 0; k < MZ; ++k) {
+            const v2f u = xA[(k >> 1) * 2 * NCOL + (k & 1)];
+            acc += h[k].x * u.x - h[k].y * u.y;
+          }
+        }
+        if (pB <= a.bx) {
+          const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+#pragma unroll
+          for (int k = 0; k < MZ; ++k) {
+            const v2f u = xB[(k >> 1) * 2 * NCOL + (k & 1)];
+            acc += h[k].x * u.x - h[k].y * u.y;
+          }
+        }
       }
     }
 #pragma unroll
@@ -579,23 +600,26 @@ static __device__ void finish16(const PixArgs& a, const float* ring_delayed, con
   float acc = 0.f;
   const int kyc = (ky <= 8) ? ky : ky - 16;
   if (kyc >= -a.by && kyc <= a.by) {
-    const float2* X = a.st + pix * NCOL * MZ;
+    const float2* X = a.st + pix * NCOL * MZ;   // layout: st16_index
     for (int h = 0; h < 2; ++h) {
       const int p = h ? pB : pA;
       if (p > a.bx) continue;
-      const float2* xc = X + (p * MY + ky) * MZ;
+      const float2* xc = X + st16_index(p, ky, 0);   // element kz at xc[st16_index(0, 0, kz)]
       const float wgt = (p == 0) ? 1.f : 2.f;
       if (learned) {
 #pragma unroll
         for (int k = 0; k < MZ; ++k) {
           const float2 c = coeff16(p, kyc, k, vx, vy, a.dx, a.dy, a.dt);
-          const float2 xv = xc[k];
+          const float2 xv = xc[st16_index(0, 0, k)];
           acc += wgt * (c.x * xv.x - c.y * xv.y);
         }
       } else {
         const float2* hp = a.htab + (((size_t)fi * (a.bx + 1) + p) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) acc += hp[k].x * xc[k].x - hp[k].y * xc[k].y;
+        for (int k = 0; k < MZ; ++k) {
+          const float2 xv = xc[st16_index(0, 0, k)];
+          acc += hp[k].x * xv.x - hp[k].y * xv.y;
+        }
       }
     }
   }

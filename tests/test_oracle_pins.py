@@ -76,6 +76,30 @@ def test_coefficients_eq8_equal_dft_of_eq2(orc, M, B, v):
     assert np.abs(Hk - ref).max() <= 1e-13
 
 
+# Eq. (8) at a bin depends on the velocity only through phi = vx kx/Mx +
+# vy ky/My, and only through phi mod 1 (the sign change of D_Mz(w + 1) for
+# even Mz cancels that of exp(j 2 pi (m'z - Dz))).  The 16x16x8 kernel relies
+# on this to read its coefficients from a table indexed by phi mod 1.
+@pytest.mark.parametrize("M,B", [((16, 16, 8), (6, 6)), ((9, 9, 5), (3, 3)), ((8, 8, 4), (3, 3))])
+def test_coefficients_eq8_periodic_in_phi(orc, M, B):
+    rng = np.random.default_rng(17)
+    cfg = _cfg(orc, 4, 4, M, Bx=B[0], By=B[1])
+    for _ in range(12):
+        kx, ky = int(rng.integers(-B[0], B[0] + 1)), int(rng.integers(-B[1], B[1] + 1))
+        v = rng.uniform(-4, 4, size=2)
+        n = int(rng.integers(-3, 4))
+        if kx != 0:
+            w = (v[0] + n * M[0] / kx, v[1])
+        elif ky != 0:
+            w = (v[0] + rng.uniform(-4, 4), v[1] + n * M[1] / ky)   # kx = 0: vx does not enter
+        else:
+            w = tuple(rng.uniform(-4, 4, size=2))                    # phi = 0 for any v
+        a = orc.coeffs(cfg, *v)[kx % M[0], ky % M[1]]
+        b = orc.coeffs(cfg, *w)[kx % M[0], ky % M[1]]
+        assert np.abs(a).max() > 0
+        assert np.abs(a - b).max() <= 1e-12, (kx, ky, v, w)
+
+
 # P5 -- the frequency-domain background estimate (eq. 4) equals the direct
 # 3-D convolution of eq. (1).
 @pytest.mark.parametrize("M", [(8, 8, 4), (9, 9, 5), (6, 5, 4)])
