@@ -231,6 +231,7 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 generic, 2 wave-per-anchor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-velocity leg")
     ap.add_argument("--batch24", action="store_true",
                     help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -321,7 +322,7 @@ def main():
         "kernel_ms": {"pixel": pix_ms, "row": kms[1][0] / max(kms[1][1], 1), "ingest": kms[2][0] / max(kms[2][1], 1)},
         "wall_s": wall,
     }
-    lr = learned_leg(dev, sc, M, g, min(args.steps, 200), args.warmup)
+    lr = None if args.no_learned else learned_leg(dev, sc, M, g, min(args.steps, 200), args.warmup)
     if lr is not None:
         lr["vs_plain"] = lr["value"] / value
         res["learned"] = lr

@@ -182,3 +182,21 @@ def test_short_training_reduces_loss():
     assert X.shape == (5000, 1152) and lab.shape == (5000, 2)
     tr, losses = learned.train(X, lab, steps=300, batch=1024)
     assert losses[-1][1] < 0.7 * losses[0][1], losses
+
+
+def test_trained_network_against_search():
+    """The shipped network (trained by paper_1408_3526_amd.learned on seeds
+    1000-1049) on a held-out seed: the learned mode's PEF residual is within
+    5% of the plain search's (its acceptance bar), it is confident on part of
+    the frame, and the gain is printed (residual, velocity RMSE)."""
+    import os
+
+    from paper_1408_3526_amd import learned
+    if not os.path.exists(learned.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights shipped")
+    w = np.load(learned.DEFAULT_WEIGHTS)
+    r = learned.evaluate(w, [2100], H=256, W=320, T=30)
+    s, l = r["search"], r["learned"]
+    print("search", s, "learned", l)
+    assert l["residual_rms"] <= 1.05 * s["residual_rms"]
+    assert l["fallback_rate"] < 1.0
