@@ -170,8 +170,10 @@ static __device__ __forceinline__ unsigned short to_bf16(float f) {
 }
 
 // MODE: 0 plain search; 1 plain search that also writes the learned model's
-// input features; 2 learned mode (features, instantaneous search index for
-// the fallback; the background estimate is made later by finish16).
+// input features; 2 learned mode, first pass: features, and the complete
+// fallback result (instantaneous search, i.e. no smoothed-R state, its
+// background estimate and output), which finish16 overwrites where the
+// network is confident.
 template <int MODE>
 static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   lds_v2* s_all = (lds_v2*)(smem);
@@ -189,7 +191,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     const float4* tc = reinterpret_cast<const float4*>(a.tabC);
     for (int i = threadIdx.x; i < 4 * nvy; i += 256) s_tab[i] = v4f{tb[i].x, tb[i].y, tb[i].z, tb[i].w};
     for (int i = threadIdx.x; i < 4 * nvx; i += 256) s_tab[4 * NV1_MAX + i] = v4f{tc[i].x, tc[i].y, tc[i].z, tc[i].w};
-    if (MODE != 2 && a.gtab != nullptr) {
+    if (a.gtab != nullptr) {
       for (int i = threadIdx.x; i < a.lat_q * MZ; i += 256) s_g[i] = v2f{a.gtab[i].x, a.gtab[i].y};
       for (int i = threadIdx.x; i < ETAB; i += 256) {
         const int p = i / 17, kc = i % 17 - 8;
@@ -217,7 +219,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
   const float2 wy = a.twy[ky];
   const int kyc = (ky <= 8) ? ky : ky - 16;
   // lattice background coefficients (table and spatial factors in LDS)
-  const bool lattice = (MODE != 2) && (a.gtab != nullptr);
+  const bool lattice = a.gtab != nullptr;
 
   const size_t HW = (size_t)a.H * a.W;
   const float2* rsA = a.rs + (size_t)pA * HW + x;
@@ -348,6 +350,8 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       const int off0 = hC * nvx + ixC, offl = (nvy - 1) * nvx + ixC;
 #pragma unroll
       for (int j = 0; j < NC_IT; ++j) rprev[j] = rp[(unsigned)min(off0 + 3 * j * nvx, offl)];
+    }
+    {
       const int xs = x - a.dx, ys = y - a.dy;
       if (ring_delayed != nullptr && xs >= 0 && ys >= 0) idel = ring_delayed[(size_t)ys * a.W + xs];
     }
@@ -484,10 +488,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       amax_merge(bv, bi, v2, i2);
     }
     const int istar = (bi < nv) ? bi : 0;
-    if (MODE == 2) {
-      if (lane == 0) a.fidx[pix] = istar;
-      continue;
-    }
+    if (MODE == 2 && lane == 0) a.fidx[pix] = istar;
 
     // ---- background estimate with the chosen velocity's coefficients.  It
     // needs this row's posterior state again: it is read back (written above,
@@ -583,9 +584,10 @@ static __device__ __forceinline__ float2 coeff16(int kx, int kyc, int kz, float 
   return f2(g * cs, g * sn);
 }
 
-// Learned mode, second pass: one wavefront per anchor.  Velocity = the
-// network's (vx, vy) where its confidence >= thr, else the search index
-// written by pixel16_tile<2>; background estimate and output.
+// Learned mode, second pass: one wavefront per anchor.  Where the network's
+// confidence >= thr: velocity = its (vx, vy), background estimate with eq. (8)
+// at that continuous velocity, output.  Elsewhere the wavefront leaves at once
+// (the search fallback written by pixel16_tile<2> stands).
 static __device__ void finish16(const PixArgs& a, const float* ring_delayed, const float* vc, float thr,
                                 int x, int y) {
   const int lane = threadIdx.x & 63;
@@ -593,10 +595,8 @@ static __device__ void finish16(const PixArgs& a, const float* ring_delayed, con
   const int pA = r, pB = r + 4;
   const size_t pix = (size_t)y * a.W + x;
   const float conf = vc[3 * pix + 2];
-  const bool learned = conf >= thr;
-  const int fi = a.fidx[pix];
-  const float vx = learned ? vc[3 * pix] : a.gx[fi % a.nvx];
-  const float vy = learned ? vc[3 * pix + 1] : a.gy[fi / a.nvx];
+  if (!(conf >= thr)) return;          // the first pass already wrote the search fallback
+  const float vx = vc[3 * pix], vy = vc[3 * pix + 1];
   float acc = 0.f;
   const int kyc = (ky <= 8) ? ky : ky - 16;
   if (kyc >= -a.by && kyc <= a.by) {
@@ -606,20 +606,11 @@ static __device__ void finish16(const PixArgs& a, const float* ring_delayed, con
       if (p > a.bx) continue;
       const float2* xc = X + st16_index(p, ky, 0);   // element kz at xc[st16_index(0, 0, kz)]
       const float wgt = (p == 0) ? 1.f : 2.f;
-      if (learned) {
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) {
-          const float2 c = coeff16(p, kyc, k, vx, vy, a.dx, a.dy, a.dt);
-          const float2 xv = xc[st16_index(0, 0, k)];
-          acc += wgt * (c.x * xv.x - c.y * xv.y);
-        }
-      } else {
-        const float2* hp = a.htab + (((size_t)fi * (a.bx + 1) + p) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
-#pragma unroll
-        for (int k = 0; k < MZ; ++k) {
-          const float2 xv = xc[st16_index(0, 0, k)];
-          acc += hp[k].x * xv.x - hp[k].y * xv.y;
-        }
+      for (int k = 0; k < MZ; ++k) {
+        const float2 c = coeff16(p, kyc, k, vx, vy, a.dx, a.dy, a.dt);
+        const float2 xv = xc[st16_index(0, 0, k)];
+        acc += wgt * (c.x * xv.x - c.y * xv.y);
       }
     }
   }
@@ -631,7 +622,7 @@ static __device__ void finish16(const PixArgs& a, const float* ring_delayed, con
     if (!isfinite(idel)) idel = 0.f;
     a.out[pix] = idel - acc;
     a.vxy[pix] = make_float2(vx, vy);
-    a.vidx[pix] = learned ? -2 : fi;
+    a.vidx[pix] = -2;
   }
 }
 
