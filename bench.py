@@ -79,8 +79,16 @@ def copy_calibration(nbytes=1 << 30, reps=10):
     for _ in range(reps):
         dst.copy_(src)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
     print(json.dumps({"copy_bytes_read_per_launch": nbytes, "copy_bytes_written_per_launch": nbytes,
-                      "launches": reps}), flush=True)
+                      "launches": 2 * reps, "ms_per_copy": ms,
+                      "read_plus_write_GBps": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
 
 
 # Batched streams: (count, H, W, window, velocity grid (lo, hi, step), targets)

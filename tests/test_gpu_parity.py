@@ -263,6 +263,24 @@ def test_state_errors():
     f.close()
 
 
+def test_kernel_variant_limits():
+    """The one-wavefront-per-anchor kernel takes at most 21 candidates per
+    axis; beyond that the automatic choice is the generic kernel and an
+    explicit request is refused."""
+    b = _binding()
+    g21, g23 = scenes.grid(-5, 5, 0.5), scenes.grid(-5.5, 5.5, 0.5)
+    assert len(g21) == 21 and len(g23) == 23
+    f = b.Filter(20, 20, 16, 16, 8, g21, g21)
+    assert f.kernel_name() == "k_pixel16"
+    f.close()
+    f = b.Filter(20, 20, 16, 16, 8, g21, g23)
+    assert f.kernel_name() == "k_pixel<16,16,8>"
+    f.close()
+    with pytest.raises(b.RmdfError) as e:
+        b.Filter(20, 20, 16, 16, 8, g23, g21, kernel_variant=2)
+    assert e.value.status == b.RMDF_E_UNSUPPORTED
+
+
 def _sampled_full_size(orc, sc, M, g, pts, T, **kw):
     """Full-size run on the GPU; the oracle computes the sampled anchors one by
     one from the direct window spectrum."""
