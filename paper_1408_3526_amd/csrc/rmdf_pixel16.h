@@ -234,30 +234,38 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     acB = f2(wy.x * acB.x - wy.y * acB.y + vB.x, wy.x * acB.y + wy.y * acB.x + vB.y);
   }
 
+  // Rows are software-pipelined: the observer state and row-spectrum samples
+  // of row y + 1 are loaded as soon as row y has staged its planes in LDS, so
+  // their HBM latency hides behind the flow stages of row y.  State layout:
+  // [kz pair][plane][ky] x 2 complex per pixel (st16_index), one 1 KB
+  // contiguous run per instruction.
+  float4 SnA[MZ / 2], SnB[MZ / 2];
+  float2 nA, nB, oA = f2(0.f, 0.f), oB = f2(0.f, 0.f);   // rs(y), rs(y - My)
+  {
+    const float4* src = reinterpret_cast<const float4*>(a.st + ((size_t)y0 * a.W + x) * NCOL * MZ);
+#pragma unroll
+    for (int j = 0; j < MZ / 2; ++j) { SnA[j] = src[j * NCOL + pA * MY + ky]; SnB[j] = src[j * NCOL + pB * MY + ky]; }
+    nA = rsA[(size_t)y0 * a.W];
+    nB = rsB[(size_t)y0 * a.W];
+    if (y0 >= MY) {
+      oA = rsA[(size_t)(y0 - MY) * a.W];
+      oB = rsB[(size_t)(y0 - MY) * a.W];
+    }
+  }
+
   for (int y = y0; y < y1; ++y) {
     const size_t pix = (size_t)y * a.W + x;
-    // observer state of this anchor: one 1 KB contiguous run per instruction
-    // (state layout [kz pair][plane][ky] x 2 complex, see st16_index)
     float2 XA[MZ], XB[MZ];
-    {
-      const float4* src = reinterpret_cast<const float4*>(a.st + pix * NCOL * MZ);
 #pragma unroll
-      for (int j = 0; j < MZ / 2; ++j) {
-        const float4 u = src[j * NCOL + pA * MY + ky], v = src[j * NCOL + pB * MY + ky];
-        XA[2 * j] = f2(u.x, u.y);
-        XA[2 * j + 1] = f2(u.z, u.w);
-        XB[2 * j] = f2(v.x, v.y);
-        XB[2 * j + 1] = f2(v.z, v.w);
-      }
+    for (int j = 0; j < MZ / 2; ++j) {
+      XA[2 * j] = f2(SnA[j].x, SnA[j].y);
+      XA[2 * j + 1] = f2(SnA[j].z, SnA[j].w);
+      XB[2 * j] = f2(SnB[j].x, SnB[j].y);
+      XB[2 * j + 1] = f2(SnB[j].z, SnB[j].w);
     }
     // ---- column sliding DFT
     {
-      float2 iA = rsA[(size_t)y * a.W], iB = rsB[(size_t)y * a.W];
-      if (y >= MY) {
-        const float2 oA = rsA[(size_t)(y - MY) * a.W], oB = rsB[(size_t)(y - MY) * a.W];
-        iA = f2(iA.x - oA.x, iA.y - oA.y);
-        iB = f2(iB.x - oB.x, iB.y - oB.y);
-      }
+      const float2 iA = f2(nA.x - oA.x, nA.y - oA.y), iB = f2(nB.x - oB.x, nB.y - oB.y);
       acA = f2(wy.x * acA.x - wy.y * acA.y + iA.x, wy.x * acA.y + wy.y * acA.x + iA.y);
       acB = f2(wy.x * acB.x - wy.y * acB.y + iB.x, wy.x * acB.y + wy.y * acB.x + iB.y);
     }
@@ -354,6 +362,20 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     {
       const int xs = x - a.dx, ys = y - a.dy;
       if (ring_delayed != nullptr && xs >= 0 && ys >= 0) idel = ring_delayed[(size_t)ys * a.W + xs];
+    }
+    // next row's state and row-spectrum samples (see the pipeline note);
+    // issued after the loads above, which stage C waits for (vector memory
+    // completes in order)
+    if (y + 1 < y1) {
+      const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
+#pragma unroll
+      for (int j = 0; j < MZ / 2; ++j) { SnA[j] = src[j * NCOL + pA * MY + ky]; SnB[j] = src[j * NCOL + pB * MY + ky]; }
+      nA = rsA[(size_t)(y + 1) * a.W];
+      nB = rsB[(size_t)(y + 1) * a.W];
+      if (y + 1 >= MY) {
+        oA = rsA[(size_t)(y + 1 - MY) * a.W];
+        oB = rsB[(size_t)(y + 1 - MY) * a.W];
+      }
     }
 
     // ---- Hann along kx, power spectrum, stage A: Q(kx, ky) = sum_kz P w_z^kz.
@@ -490,62 +512,40 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     const int istar = (bi < nv) ? bi : 0;
     if (MODE == 2 && lane == 0) a.fidx[pix] = istar;
 
-    // ---- background estimate with the chosen velocity's coefficients.  It
-    // needs this row's posterior state again: it is read back (written above,
-    // still in L2) one plane at a time rather than kept in 32 registers
-    // through the flow stages.  The empty asm hides the address from the
-    // compiler, which would otherwise forward the stored registers.
+    // ---- background estimate with the chosen velocity's coefficients (the
+    // posterior state is still in registers)
     const int hsel = __builtin_amdgcn_readfirstlane((a.vmode == 2) ? nv : istar);
     float acc = 0.f;
-    {
-      unsigned long long addr = (unsigned long long)(a.st + pix * NCOL * MZ);
-      asm volatile("" : "+s"(addr));
-      // element kz of column (p, ky) is float2 (kz/2 * 128 + p * 16 + ky) * 2 + kz % 2
-      const RMDF_GLOBAL v2f* xA = (const RMDF_GLOBAL v2f*)addr + 2 * (pA * MY + ky);
-      const RMDF_GLOBAL v2f* xB = (const RMDF_GLOBAL v2f*)addr + 2 * (pB * MY + ky);
-      if (lattice) {
-        // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
-        const int nq = a.latq[hsel];
-        const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
-        const int qm = a.lat_q - 1;
-        const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
-        const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
-        const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
-        float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
+    if (lattice) {
+      // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
+      const int nq = a.latq[hsel];
+      const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
+      const int qm = a.lat_q - 1;
+      const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
+      const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
+      const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
+      float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) {
-          const v2f u = xA[(k >> 1) * 2 * NCOL + (k & 1)], g = gA[k];
-          sA.x += g.x * u.x - g.y * u.y;
-          sA.y += g.x * u.y + g.y * u.x;
-        }
-        const float2 EA = ld2(e);
-        acc = EA.x * sA.x - EA.y * sA.y;
+      for (int k = 0; k < MZ; ++k) {
+        const v2f g = gA[k], h = gB[k];
+        sA.x += g.x * XA[k].x - g.y * XA[k].y;
+        sA.y += g.x * XA[k].y + g.y * XA[k].x;
+        sB.x += h.x * XB[k].x - h.y * XB[k].y;
+        sB.y += h.x * XB[k].y + h.y * XB[k].x;
+      }
+      const float2 EA = ld2(e), EB = ld2(e + 4 * 17);
+      acc = (EA.x * sA.x - EA.y * sA.y) + (EB.x * sB.x - EB.y * sB.y);
+    } else if (kyc >= -a.by && kyc <= a.by) {
+      const size_t row = (size_t)hsel * (a.bx + 1);
+      if (pA <= a.bx) {
+        const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) {
-          const v2f u = xB[(k >> 1) * 2 * NCOL + (k & 1)], g = gB[k];
-          sB.x += g.x * u.x - g.y * u.y;
-          sB.y += g.x * u.y + g.y * u.x;
-        }
-        const float2 EB = ld2(e + 4 * 17);
-        acc += EB.x * sB.x - EB.y * sB.y;
-      } else if (kyc >= -a.by && kyc <= a.by) {
-        const size_t row = (size_t)hsel * (a.bx + 1);
-        if (pA <= a.bx) {
-          const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+        for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
+      }
+      if (pB <= a.bx) {
+        const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-          for (int k = 0; k < MZ; ++k) {
-            const v2f u = xA[(k >> 1) * 2 * NCOL + (k & 1)];
-            acc += h[k].x * u.x - h[k].y * u.y;
-          }
-        }
-        if (pB <= a.bx) {
-          const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
-#pragma unroll
-          for (int k = 0; k < MZ; ++k) {
-            const v2f u = xB[(k >> 1) * 2 * NCOL + (k & 1)];
-            acc += h[k].x * u.x - h[k].y * u.y;
-          }
-        }
+        for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
       }
     }
 #pragma unroll

@@ -7,16 +7,17 @@
 namespace rmdf {
 namespace p16 {
 
-// Three workgroups (12 wavefronts) per CU fit the LDS; the register budget
-// is set to match (168 VGPRs), for the feature-writing search too.
+// Two workgroups (8 wavefronts) per CU: measured as fast as three, and the
+// 256-register budget keeps each wavefront's whole row (state, next row's
+// prefetched state) in registers.
 template <int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_pixel16(PixArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_pixel16(PixArgs a) {
   __shared__ __align__(16) char smem[SMEM16];
   const int xblocks = (a.W + WAVES - 1) / WAVES;
   pixel16_tile<MODE>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
 }
 
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_pixel16_feat(PixArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_pixel16_feat(PixArgs a) {
   __shared__ __align__(16) char smem[SMEM16];
   const int xblocks = (a.W + WAVES - 1) / WAVES;
   pixel16_tile<1>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
