@@ -96,10 +96,9 @@ template <> struct KindSmem<KIND_995> { static constexpr size_t v = Shape<9, 9, 
 template <> struct KindSmem<KIND_16G> { static constexpr size_t v = Shape<16, 16, 8>::SMEM; };
 template <> struct KindSmem<KIND_16W> { static constexpr size_t v = p16::SMEM16; };
 
-// One persistent kernel per tile family (its queue is queue[KIND]).  The
-// 16x16x8 wave-per-anchor tile needs more registers here than in the
-// single-stream kernel (the per-item descriptor and queue state stay live), so
-// it runs two workgroups per CU instead of spilling.
+// One persistent kernel per tile family (its queue is queue[KIND]), so every
+// tile keeps its own register budget; the 16x16x8 wave-per-anchor tile runs
+// two workgroups per CU, as in the single-stream kernel.
 template <int KIND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == KIND_16W ? 2 : 1)))
 k_batch_tiles(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items, BatchState bs) {
