@@ -41,9 +41,9 @@ def algorithmic_bytes_per_pixel_frame(M, nv):
     """Bytes the method itself must move per pixel and frame: observer state
     read + write (Mx*My*Mz reals of a Hermitian spectrum, FP32), smoothed
     autocorrelation read + write (nv FP32), frame in, delayed frame in,
-    output out, velocity (2 FP32) out."""
+    output out, velocity (2 FP32) and its grid index (int32) out."""
     Mx, My, Mz = M
-    return 2 * 4 * Mx * My * Mz + 2 * 4 * nv + 4 + 4 + 4 + 8
+    return 2 * 4 * Mx * My * Mz + 2 * 4 * nv + 4 + 4 + 4 + 8 + 4
 
 
 def kernel_source_digest():
