@@ -58,6 +58,7 @@ struct rmdf_ctx {
   int* fidx = nullptr;             // [HW] search index (fallback)
   unsigned short *h1 = nullptr, *h2 = nullptr;   // [HW][128], [HW][64] BF16
   float* vc = nullptr;             // [HW][3] network output (vx, vy, confidence)
+  int* conf_list = nullptr;        // [1 + HW]: count, then the confident anchors (pixel index)
   unsigned short *w1 = nullptr, *w2 = nullptr;   // BF16 [128][1152], [64][128]
   float *b1 = nullptr, *b2 = nullptr, *w3 = nullptr, *b3 = nullptr;
   bool weights_set = false;
@@ -402,6 +403,7 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
     if ((e = dalloc(c, &c->h1, HW * 128)) != hipSuccess) return bail(e, "hidden layer");
     if ((e = dalloc(c, &c->h2, HW * 64)) != hipSuccess) return bail(e, "hidden layer");
     if ((e = dalloc(c, &c->vc, HW * 3)) != hipSuccess) return bail(e, "network output");
+    if ((e = dalloc(c, &c->conf_list, HW + 1)) != hipSuccess) return bail(e, "confident-anchor list");
     if ((e = dalloc(c, &c->w1, (size_t)128 * 1152)) != hipSuccess) return bail(e, "weights");
     if ((e = dalloc(c, &c->w2, (size_t)64 * 128)) != hipSuccess) return bail(e, "weights");
     if ((e = dalloc(c, &c->b1, 128)) != hipSuccess) return bail(e, "weights");
@@ -470,7 +472,7 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
     timed_end(c, &ev);
     if (st != RMDF_OK) return fail(c, st, "network launch failed");
     timed_begin(c, 4, &ev);
-    e = rmdf::launch_finish16(a, c->vc, c->conf, c->stream);
+    e = rmdf::launch_finish16(a, c->vc, c->conf, c->conf_list, c->stream);
     timed_end(c, &ev);
     if (e != hipSuccess) return hip_fail(c, e, "finish kernel launch");
   }

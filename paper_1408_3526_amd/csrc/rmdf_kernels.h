@@ -58,7 +58,8 @@ hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, cons
                            bool layout16, hipStream_t s);
 bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
-hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, hipStream_t s);
+// list: [1 + H*W] ints of scratch (count, then the confident anchors)
+hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);
 hipError_t launch_ingest(const float* in, float* slot, long long n, unsigned long long* nonfinite, hipStream_t s);
 
 }  // namespace rmdf

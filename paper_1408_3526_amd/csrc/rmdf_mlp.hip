@@ -3,7 +3,8 @@
 // with ReLU; output vx, vy and a confidence logit) trained and evaluated with
 // BF16 operands on MFMA and FP32 accumulation.
 //
-//   k_gemm_nt     C[M][N] = act(A[M][K] . B[N][K]^T + bias)   (v_mfma 32x32x16 bf16)
+//   k_gemm_nt     C[M][N] = act(A[M][K] . B[N][K]^T + bias)   (v_mfma 32x32x16 bf16;
+//                 64 or 128 columns per tile)
 //   k_transpose   BF16 / FP32 -> BF16 transpose (operands of the weight-gradient GEMMs)
 //   k_head        layer 3 (64 -> 3), loss and its gradient, dH2, dW3/db3 partial sums
 //   k_infer_head  layer 3 for inference, confidence = sigmoid(logit)
@@ -19,7 +20,7 @@ namespace mlp {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int BM = 64, BK = 32;
 constexpr int LDSK = BK + 8;   // bf16 per LDS row (80 B): rows 16-byte aligned, banks spread
 
 enum : int { EPI_NONE = 0, EPI_RELU = 1, EPI_RELU_GRAD = 2 };
@@ -36,49 +37,73 @@ __device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as
 // C = epi(A . B^T + bias).  A: M x K (lda), B: N x K (ldb), BF16 row-major,
 // K contiguous.  Output FP32 (Cf) and/or BF16 (Cb), row-major ldc.
 // EPI_RELU_GRAD multiplies by (aux[m][n] > 0) where aux is BF16 (ldaux).
+// Tile BM x BN_ (BN_ = 64 or 128), four wavefronts in a 2 x 2 arrangement,
+// each owning 32 x (BN_ / 2) of C as BN_ / 64 MFMA 32x32 accumulators.  With
+// BN_ = 128 a layer of 128 outputs reads its input rows once.  The next K
+// slice's global loads are issued before the current slice's MFMAs.
+template <int BN_>
 __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restrict__ A, int lda,
                                                  const unsigned short* __restrict__ B, int ldb, int M, int N, int K,
                                                  const float* __restrict__ bias, int epi,
                                                  const unsigned short* __restrict__ aux, int ldaux,
                                                  float* __restrict__ Cf, unsigned short* __restrict__ Cb, int ldc) {
+  constexpr int NB = BN_ / 64;           // B rows per loader thread, accumulators per wavefront
   __shared__ __align__(16) unsigned short sA[BM * LDSK];
-  __shared__ __align__(16) unsigned short sB[BN * LDSK];
+  __shared__ __align__(16) unsigned short sB[BN_ * LDSK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  f32x16 acc;
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN_;
+  f32x16 acc[NB];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.f;
-  // loader: thread -> (row = tid / 4, 8 bf16 at k = (tid % 4) * 8)
+  for (int t = 0; t < NB; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+  // loader: thread -> (row = tid / 4 (+ 64 t for B), 8 bf16 at k = (tid % 4) * 8)
   const int lr = tid >> 2, lk = (tid & 3) * 8;
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+  auto load = [&](int k0, uint4& va, uint4 (&vb)[NB]) {
     const int gk = k0 + lk;
+    va = make_uint4(0, 0, 0, 0);
     if (m0 + lr < M && gk < K) va = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + lr) * lda + gk);
-    if (n0 + lr < N && gk < K) vb = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + lr) * ldb + gk);
-    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+      vb[t] = make_uint4(0, 0, 0, 0);
+      if (n0 + lr + 64 * t < N && gk < K) vb[t] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + lr + 64 * t) * ldb + gk);
+    }
+  };
+  uint4 va, vb[NB];
+  load(0, va, vb);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+    __syncthreads();                      // previous slice's MFMA reads of sA/sB are done
     *reinterpret_cast<uint4*>(&sA[lr * LDSK + lk]) = va;
-    *reinterpret_cast<uint4*>(&sB[lr * LDSK + lk]) = vb;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) *reinterpret_cast<uint4*>(&sB[(lr + 64 * t) * LDSK + lk]) = vb[t];
     __syncthreads();
+    if (k0 + BK < K) load(k0 + BK, va, vb);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int r = lane & 31, kq = kk + (lane >> 5) * 8;
       const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[(wm * 32 + r) * LDSK + kq]);
-      const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[(wn * 32 + r) * LDSK + kq]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < NB; ++t) {
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[(wn * 32 * NB + 32 * t + r) * LDSK + kq]);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+      }
     }
   }
   // D layout: column = lane % 32; row = (i / 4) * 8 + (lane / 32) * 4 + i % 4
-  const int col = n0 + wn * 32 + (lane & 31);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int row = m0 + wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
-    if (row < M && col < N) {
-      float v = acc[i] + (bias ? bias[col] : 0.f);
-      if (epi == EPI_RELU) v = v > 0.f ? v : 0.f;
-      else if (epi == EPI_RELU_GRAD) v = (bf16_float(aux[(size_t)row * ldaux + col]) > 0.f) ? v : 0.f;
-      if (Cf) Cf[(size_t)row * ldc + col] = v;
-      if (Cb) Cb[(size_t)row * ldc + col] = bf16_bits(v);
+  for (int t = 0; t < NB; ++t) {
+    const int col = n0 + wn * 32 * NB + 32 * t + (lane & 31);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = m0 + wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+      if (row < M && col < N) {
+        float v = acc[t][i] + (bias ? bias[col] : 0.f);
+        if (epi == EPI_RELU) v = v > 0.f ? v : 0.f;
+        else if (epi == EPI_RELU_GRAD) v = (bf16_float(aux[(size_t)row * ldaux + col]) > 0.f) ? v : 0.f;
+        if (Cf) Cf[(size_t)row * ldc + col] = v;
+        if (Cb) Cb[(size_t)row * ldc + col] = bf16_bits(v);
+      }
     }
   }
 }
@@ -238,10 +263,17 @@ rmdf_status rmdf_mlp_gemm_nt(const void* A, int lda, const void* B, int ldb, int
   if (!A || !B || M < 1 || N < 1 || K < 1 || (K % 8) || (lda % 8) || (ldb % 8) || (!Cf && !Cb) || epi < 0 || epi > 2 ||
       (epi == EPI_RELU_GRAD && !aux))
     return RMDF_E_INVAL;
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
-  hipLaunchKernelGGL(k_gemm_nt, grid, dim3(256), 0, S(stream), (const unsigned short*)A, lda,
-                     (const unsigned short*)B, ldb, M, N, K, bias, epi, (const unsigned short*)aux, ldaux, Cf,
-                     (unsigned short*)Cb, ldc);
+  if (N >= 128) {
+    dim3 grid((N + 127) / 128, (M + BM - 1) / BM);
+    hipLaunchKernelGGL(k_gemm_nt<128>, grid, dim3(256), 0, S(stream), (const unsigned short*)A, lda,
+                       (const unsigned short*)B, ldb, M, N, K, bias, epi, (const unsigned short*)aux, ldaux, Cf,
+                       (unsigned short*)Cb, ldc);
+  } else {
+    dim3 grid((N + 63) / 64, (M + BM - 1) / BM);
+    hipLaunchKernelGGL(k_gemm_nt<64>, grid, dim3(256), 0, S(stream), (const unsigned short*)A, lda,
+                       (const unsigned short*)B, ldb, M, N, K, bias, epi, (const unsigned short*)aux, ldaux, Cf,
+                       (unsigned short*)Cb, ldc);
+  }
   return st_of(hipGetLastError());
 }
 

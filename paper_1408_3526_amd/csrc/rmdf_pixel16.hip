@@ -23,10 +23,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   pixel16_tile<1>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
 }
 
-__global__ void __launch_bounds__(256) k_finish16(PixArgs a, const float* vc, float thr) {
-  const long long pix = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (pix >= (long long)a.H * a.W) return;
-  finish16(a, a.ring_delayed, vc, thr, (int)(pix % a.W), (int)(pix / a.W));
+// Learned mode, second pass.  k_conf_list compacts the anchors whose
+// confidence clears the threshold (list[0] = count, list[1..] = pixel
+// indices; one atomic per wavefront); k_finish16 then runs one wavefront per
+// listed anchor, its fixed grid striding over the list.
+__global__ void k_conf_reset(int* list) {
+  if (threadIdx.x == 0) list[0] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_conf_list(const float* __restrict__ vc, long long n, float thr,
+                                                   int* __restrict__ list) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const bool ok = (i < n) && (vc[3 * i + 2] >= thr);
+  const unsigned long long m = __ballot(ok);
+  if (m == 0) return;
+  const int lane = threadIdx.x & 63;
+  const int before = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+  int base = 0;
+  if (lane == __ffsll((long long)m) - 1) base = atomicAdd(list, __popcll(m));
+  base = __shfl(base, __ffsll((long long)m) - 1, 64);
+  if (ok) list[1 + base + before] = (int)i;
+}
+
+constexpr int FINISH_BLOCKS = 2048;
+
+__global__ void __launch_bounds__(256) k_finish16(PixArgs a, const float* vc, float thr, const int* list) {
+  const int count = list[0];
+  const int nwaves = FINISH_BLOCKS * 4;
+  for (int j = blockIdx.x * 4 + (threadIdx.x >> 6); j < count; j += nwaves) {
+    const int pix = list[1 + j];
+    finish16(a, a.ring_delayed, vc, thr, pix % a.W, pix / a.W);
+  }
 }
 
 }  // namespace p16
@@ -44,9 +71,11 @@ hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, hipStream_t s) {
+hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s) {
   const long long n = (long long)a.H * a.W;
-  hipLaunchKernelGGL(p16::k_finish16, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, a, vc, thr);
+  hipLaunchKernelGGL(p16::k_conf_reset, dim3(1), dim3(64), 0, s, list);
+  hipLaunchKernelGGL(p16::k_conf_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, vc, n, thr, list);
+  hipLaunchKernelGGL(p16::k_finish16, dim3(p16::FINISH_BLOCKS), dim3(256), 0, s, a, vc, thr, list);
   return hipGetLastError();
 }
 
