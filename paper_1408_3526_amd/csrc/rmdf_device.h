@@ -101,9 +101,11 @@ static __device__ void row_chunk(const float* __restrict__ f, float2* __restrict
     }
   }
   __syncthreads();
+  // row spectra layout [y][x][plane]: the planes of a pixel are adjacent, so
+  // the per-pixel kernels read one contiguous run per row and workgroup
   for (int i = threadIdx.x; i < NP * RCX; i += blockDim.x) {
-    const int p = i / RCX, xi = i % RCX;
-    if (x0 + xi < W) rs[((size_t)p * H + y) * W + x0 + xi] = s_out[p * RCX + xi];
+    const int xi = i / NP, p = i % NP;
+    if (x0 + xi < W) rs[((size_t)y * W + x0 + xi) * NP + p] = s_out[p * RCX + xi];
   }
 }
 
@@ -168,7 +170,7 @@ static __device__ void pixel_tile(const PixArgs& a, const float* ring_delayed, i
     for (int m = 0; m < MY; ++m) {
       const int yy = y0 - 1 - m;
       if (yy < 0) break;
-      const float2 v = a.rs[((size_t)p * a.H + yy) * a.W + x];
+      const float2 v = a.rs[((size_t)yy * a.W + x) * NP + p];
       const float2 w = s_twy[(ky * m) % MY];
       acol = cadd(acol, cmul(w, v));
     }
@@ -189,8 +191,8 @@ static __device__ void pixel_tile(const PixArgs& a, const float* ring_delayed, i
     const size_t pix = (size_t)y * a.W + x;
     // ---- column sliding DFT: comb on the row spectra, resonator w_y^ky
     if (col_ok) {
-      float2 in = a.rs[((size_t)p * a.H + y) * a.W + x];
-      if (y >= MY) in = csub(in, a.rs[((size_t)p * a.H + (y - MY)) * a.W + x]);
+      float2 in = a.rs[((size_t)y * a.W + x) * NP + p];
+      if (y >= MY) in = csub(in, a.rs[((size_t)(y - MY) * a.W + x) * NP + p]);
       acol = cadd(cmul(wy, acol), in);
     }
     const float2 s2 = cscale(acol, a.inv_sqrt_my);

@@ -18,7 +18,7 @@ struct PixArgs {
   int vmode;                   // 0 search, 2 fixed velocity
   float alpha, inv_sqrt_my;
   float fvx, fvy;
-  const float2* rs;            // row spectra [planes][H][W]
+  const float2* rs;            // row spectra [H][W][planes]
   float2* st;                  // observer state [H][W][planes*My][Mz] (16x16x8 wave-per-anchor
                                // kernel: [H][W][Mz/2][planes*My][2])
   float* rsm;                  // smoothed autocorrelation [H][W][nv]

@@ -4,7 +4,7 @@
 // Per frame (all on one stream):
 //   k_ingest  : frame -> delay ring slot, non-finite samples -> 0 (counted)
 //   k_row     : row sliding DFT (comb x(n) - x(n-M) into resonators w^k,
-//               Sec. 1, eq. 6-7) -> row spectra rs[plane][y][x]
+//               Sec. 1, eq. 6-7) -> row spectra rs[y][x][plane]
 //   k_pixel   : per anchor (x, y): column sliding DFT, temporal deadbeat
 //               observer (state streamed once), high-pass + Hann + power
 //               spectrum (eq. 9), autocorrelation on the candidate grid at

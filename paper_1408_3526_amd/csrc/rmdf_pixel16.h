@@ -221,15 +221,16 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
   // lattice background coefficients (table and spatial factors in LDS)
   const bool lattice = a.gtab != nullptr;
 
-  const size_t HW = (size_t)a.H * a.W;
-  const float2* rsA = a.rs + (size_t)pA * HW + x;
-  const float2* rsB = a.rs + (size_t)pB * HW + x;
+  // row spectra [y][x][plane]: element (row yy) at rsA[yy * rstride]
+  const size_t rstride = (size_t)a.W * 8;
+  const float2* rsA = a.rs + (size_t)x * 8 + pA;
+  const float2* rsB = a.rs + (size_t)x * 8 + pB;
 
   // column sliding DFT seeded with the 16 rows above the tile (Horner form of
   // the direct DFT: the same resonator run over those rows)
   float2 acA = f2(0.f, 0.f), acB = f2(0.f, 0.f);
   for (int yy = max(0, y0 - MY); yy < y0; ++yy) {
-    const float2 vA = rsA[(size_t)yy * a.W], vB = rsB[(size_t)yy * a.W];
+    const float2 vA = rsA[(size_t)yy * rstride], vB = rsB[(size_t)yy * rstride];
     acA = f2(wy.x * acA.x - wy.y * acA.y + vA.x, wy.x * acA.y + wy.y * acA.x + vA.y);
     acB = f2(wy.x * acB.x - wy.y * acB.y + vB.x, wy.x * acB.y + wy.y * acB.x + vB.y);
   }
@@ -245,11 +246,11 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     const float4* src = reinterpret_cast<const float4*>(a.st + ((size_t)y0 * a.W + x) * NCOL * MZ);
 #pragma unroll
     for (int j = 0; j < MZ / 2; ++j) { SnA[j] = src[j * NCOL + pA * MY + ky]; SnB[j] = src[j * NCOL + pB * MY + ky]; }
-    nA = rsA[(size_t)y0 * a.W];
-    nB = rsB[(size_t)y0 * a.W];
+    nA = rsA[(size_t)y0 * rstride];
+    nB = rsB[(size_t)y0 * rstride];
     if (y0 >= MY) {
-      oA = rsA[(size_t)(y0 - MY) * a.W];
-      oB = rsB[(size_t)(y0 - MY) * a.W];
+      oA = rsA[(size_t)(y0 - MY) * rstride];
+      oB = rsB[(size_t)(y0 - MY) * rstride];
     }
   }
 
@@ -370,11 +371,11 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
 #pragma unroll
       for (int j = 0; j < MZ / 2; ++j) { SnA[j] = src[j * NCOL + pA * MY + ky]; SnB[j] = src[j * NCOL + pB * MY + ky]; }
-      nA = rsA[(size_t)(y + 1) * a.W];
-      nB = rsB[(size_t)(y + 1) * a.W];
+      nA = rsA[(size_t)(y + 1) * rstride];
+      nB = rsB[(size_t)(y + 1) * rstride];
       if (y + 1 >= MY) {
-        oA = rsA[(size_t)(y + 1 - MY) * a.W];
-        oB = rsB[(size_t)(y + 1 - MY) * a.W];
+        oA = rsA[(size_t)(y + 1 - MY) * rstride];
+        oB = rsB[(size_t)(y + 1 - MY) * rstride];
       }
     }
 
