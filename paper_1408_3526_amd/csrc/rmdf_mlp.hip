@@ -20,8 +20,8 @@ namespace mlp {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int BM = 64, BK = 32;
-constexpr int LDSK = BK + 8;   // bf16 per LDS row (80 B): rows 16-byte aligned, banks spread
+constexpr int BM = 64, BK = 64;
+constexpr int LDSK = BK + 8;   // bf16 per LDS row (144 B): rows 16-byte aligned, banks spread
 
 enum : int { EPI_NONE = 0, EPI_RELU = 1, EPI_RELU_GRAD = 2 };
 
@@ -39,8 +39,9 @@ __device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as
 // EPI_RELU_GRAD multiplies by (aux[m][n] > 0) where aux is BF16 (ldaux).
 // Tile BM x BN_ (BN_ = 64 or 128), four wavefronts in a 2 x 2 arrangement,
 // each owning 32 x (BN_ / 2) of C as BN_ / 64 MFMA 32x32 accumulators.  With
-// BN_ = 128 a layer of 128 outputs reads its input rows once.  The next K
-// slice's global loads are issued before the current slice's MFMAs.
+// BN_ = 128 a layer of 128 outputs reads its input rows once.  K advances
+// 64 at a time (128 contiguous bytes per row); the next K slice's global loads
+// are issued before the current slice's MFMAs.
 template <int BN_>
 __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restrict__ A, int lda,
                                                  const unsigned short* __restrict__ B, int ldb, int M, int N, int K,
@@ -58,25 +59,38 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restric
   for (int t = 0; t < NB; ++t)
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
-  // loader: thread -> (row = tid / 4 (+ 64 t for B), 8 bf16 at k = (tid % 4) * 8)
-  const int lr = tid >> 2, lk = (tid & 3) * 8;
-  auto load = [&](int k0, uint4& va, uint4 (&vb)[NB]) {
-    const int gk = k0 + lk;
-    va = make_uint4(0, 0, 0, 0);
-    if (m0 + lr < M && gk < K) va = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + lr) * lda + gk);
+  // loader: 8 bf16 (16 B) per piece; piece q -> row q / (BK / 8), k = (q % (BK / 8)) * 8,
+  // so each row's BK values (128 B) are read as one contiguous run
+  constexpr int KP = BK / 8;                 // pieces per row
+  constexpr int LA = BM * KP / 256, LB = BN_ * KP / 256;
+  auto load = [&](int k0, uint4 (&va)[LA], uint4 (&vb)[LB]) {
 #pragma unroll
-    for (int t = 0; t < NB; ++t) {
+    for (int t = 0; t < LA; ++t) {
+      const int q = tid + 256 * t, r = q / KP, gk = k0 + (q % KP) * 8;
+      va[t] = make_uint4(0, 0, 0, 0);
+      if (m0 + r < M && gk < K) va[t] = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + r) * lda + gk);
+    }
+#pragma unroll
+    for (int t = 0; t < LB; ++t) {
+      const int q = tid + 256 * t, r = q / KP, gk = k0 + (q % KP) * 8;
       vb[t] = make_uint4(0, 0, 0, 0);
-      if (n0 + lr + 64 * t < N && gk < K) vb[t] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + lr + 64 * t) * ldb + gk);
+      if (n0 + r < N && gk < K) vb[t] = *reinterpret_cast<const uint4*>(B + (size_t)(n0 + r) * ldb + gk);
     }
   };
-  uint4 va, vb[NB];
+  uint4 va[LA], vb[LB];
   load(0, va, vb);
   for (int k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();                      // previous slice's MFMA reads of sA/sB are done
-    *reinterpret_cast<uint4*>(&sA[lr * LDSK + lk]) = va;
 #pragma unroll
-    for (int t = 0; t < NB; ++t) *reinterpret_cast<uint4*>(&sB[(lr + 64 * t) * LDSK + lk]) = vb[t];
+    for (int t = 0; t < LA; ++t) {
+      const int q = tid + 256 * t;
+      *reinterpret_cast<uint4*>(&sA[(q / KP) * LDSK + (q % KP) * 8]) = va[t];
+    }
+#pragma unroll
+    for (int t = 0; t < LB; ++t) {
+      const int q = tid + 256 * t;
+      *reinterpret_cast<uint4*>(&sB[(q / KP) * LDSK + (q % KP) * 8]) = vb[t];
+    }
     __syncthreads();
     if (k0 + BK < K) load(k0 + BK, va, vb);
 #pragma unroll
