@@ -70,10 +70,13 @@ def _copy_to(ptr, src):
     torch.cuda.synchronize()
 
 
-def test_batch_matches_oracle(orc):
+@pytest.mark.parametrize("variant", [0, 1])
+def test_batch_matches_oracle(orc, variant):
+    """Every stream against the oracle; variant 1 puts the 16x16x8 stream on
+    the generic tile kernel."""
     from paper_1408_3526_amd import binding
     st = _streams()
-    b = binding.Batch(st)
+    b = binding.Batch(st, kernel_variant=variant)
     dev = [torch.from_numpy(s["frames"]).cuda() for s in st]
     T = 10
     for t in range(T):

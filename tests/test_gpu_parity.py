@@ -165,6 +165,20 @@ def test_parity_16x16x8_coefficient_storage(orc, lo, hi, step, q):
     check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
 
 
+@pytest.mark.parametrize("H,W,tile,variant", [(3, 5, 32, 2), (17, 1, 4, 2), (1, 9, 8, 2), (3, 5, 32, 1), (20, 2, 8, 1)])
+def test_parity_16x16x8_tiny_frames(orc, H, W, tile, variant):
+    """Frames smaller than the window (every anchor is a border anchor), a
+    single column or row, tiles longer than the frame; both kernels."""
+    rng = np.random.default_rng(H * 100 + W + variant)
+    fr = (rng.normal(size=(10, H, W)) * 5 + 20).astype(np.float32)
+    g = scenes.grid(-2, 2, 1.0)
+    M = (16, 16, 8)
+    gres = run_gpu(fr, M, g, g, tile_rows=tile, kernel_variant=variant)
+    r = orc.run(_cfg(orc, H, W, M, g, g), fr, want_rs=True)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, fr, len(g), g, g)
+
+
 def test_parity_paper_configuration(orc):
     """The paper's parameters: 9x9x5 window (K = 4, 4, 2), B = 3, m' = K,
     17x17 grid at 0.25 px/frame, on the paper's simulated scene."""
