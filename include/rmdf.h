@@ -67,7 +67,9 @@ typedef struct {
   int velocity_mode;        /* rmdf_velocity_mode                              */
   float fixed_vx, fixed_vy; /* velocity used by RMDF_VEL_FIXED                  */
   float conf_threshold;     /* RMDF_VEL_LEARNED: search below this confidence  */
-  int tile_rows;            /* rows per work tile of the pixel kernel; 0: auto  */
+  int tile_rows;            /* rows per work tile of the pixel kernel; 0: auto
+                               (32, halved down to 1 while the frame has fewer
+                               than 2048 work tiles)                           */
   int kernel_variant;       /* per-pixel kernel: 0 auto, 1 generic (LDS-staged,
                                any compiled shape), 2 one wavefront per anchor
                                (16x16x8, at most 21 candidates per axis)       */
@@ -183,6 +185,9 @@ rmdf_status rmdf_mlp_to_bf16(const float *in, void *out_bf16, long long n, void 
 /* Per-pixel kernel variant the context launches (1 generic, 2 one wavefront
  * per anchor), after resolving kernel_variant = 0. */
 rmdf_status rmdf_kernel_variant(const rmdf_ctx *ctx, int *variant);
+
+/* Rows per work tile of the pixel kernel, after resolving tile_rows = 0. */
+rmdf_status rmdf_tile_rows(const rmdf_ctx *ctx, int *tile_rows);
 
 /* How the wavefront-per-anchor kernel stores the background coefficients of
  * eq. (8): *lattice_q = 16 s when every candidate velocity (and the fixed

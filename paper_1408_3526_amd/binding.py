@@ -58,6 +58,7 @@ _SIGS = {
     "rmdf_device_bytes": (_I, [_VP, ctypes.POINTER(_SZ)]),
     "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_coeff_lattice": (_I, [_VP, ctypes.POINTER(_I)]),
+    "rmdf_tile_rows": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
     "rmdf_mlp_set_weights": (_I, [_VP, _VP, _SZ]),
@@ -277,6 +278,12 @@ class Filter:
         _check(lib().rmdf_kernel_variant(self.ctx, ctypes.byref(v)), self.ctx)
         Mx, My, Mz = self.M
         return "k_pixel16" if v.value == 2 else "k_pixel<%d,%d,%d>" % (Mx, My, Mz)
+
+    def tile_rows(self) -> int:
+        """Rows per work tile of the pixel kernel (after the automatic choice)."""
+        v = ctypes.c_int()
+        _check(lib().rmdf_tile_rows(self.ctx, ctypes.byref(v)), self.ctx)
+        return v.value
 
     def coeff_lattice(self) -> int:
         """16 s when the background coefficients use the lattice table (grid

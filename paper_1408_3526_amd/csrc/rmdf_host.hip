@@ -372,8 +372,10 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   c->Bx = Bx; c->By = By; c->dx = dx; c->dy = dy; c->dt = dt;
   c->alpha = alpha; c->vmode = p.velocity_mode; c->fvx = p.fixed_vx; c->fvy = p.fixed_vy;
   c->conf = p.conf_threshold;
-  c->TY = p.tile_rows > 0 ? p.tile_rows : 32;
   c->variant = p.kernel_variant != 0 ? p.kernel_variant : (w16 ? 2 : 1);
+  c->TY = p.tile_rows > 0 ? p.tile_rows
+                          : rmdf::auto_tile_rows(H, W, c->variant == 2 ? rmdf::p16_block_columns()
+                                                                        : rmdf::pixel_block_columns(Kx, Ky, Kt));
   c->write_features = p.write_features ? 1 : 0;
   c->nring = dt + 1;
   // NULL: the device's default (null) stream, which is also torch's default
@@ -634,6 +636,12 @@ rmdf_status rmdf_learned_output(rmdf_ctx* c, float* vc_dev) {
 rmdf_status rmdf_kernel_variant(const rmdf_ctx* c, int* variant) {
   if (!c || !variant) return RMDF_E_INVAL;
   *variant = c->variant;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_tile_rows(const rmdf_ctx* c, int* tile_rows) {
+  if (!c || !tile_rows) return RMDF_E_INVAL;
+  *tile_rows = c->TY;
   return RMDF_OK;
 }
 

@@ -51,12 +51,17 @@ struct PixArgs {
 
 bool shape_supported(int mx, int my, int mz);
 int planes_for(int mx);
+// anchors (columns) one workgroup of the generic pixel kernel covers per row
+int pixel_block_columns(int mx, int my, int mz);
+// default rows per work tile for an H x W frame
+int auto_tile_rows(int H, int W, int block_columns);
 hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s);
 hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s);
 // layout16: the state is in the wave-per-anchor 16x16x8 layout
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
                            bool layout16, hipStream_t s);
 bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
+int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anchor kernel
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 // list: [1 + H*W] ints of scratch (count, then the confident anchors)
 hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);

@@ -128,6 +128,23 @@ bool shape_supported(int mx, int my, int mz) {
 
 int planes_for(int mx) { return (mx % 2 == 0) ? mx / 2 : (mx + 1) / 2; }
 
+int pixel_block_columns(int mx, int my, int mz) {
+  if (mx == 8 && my == 8 && mz == 4) return Shape<8, 8, 4>::PPB;
+  if (mx == 16 && my == 16 && mz == 8) return Shape<16, 16, 8>::PPB;
+  if (mx == 9 && my == 9 && mz == 5) return Shape<9, 9, 5>::PPB;
+  return 1;
+}
+
+int auto_tile_rows(int H, int W, int block_columns) {
+  // 32 rows per tile where the frame has enough tiles to fill the chip
+  // (2048 workgroups, 8 per CU); fewer rows on smaller frames, where a tile's
+  // rows run one after another and the launch would otherwise be latency-bound
+  const long long xb = (W + block_columns - 1) / block_columns;
+  int ty = 32;
+  while (ty > 1 && xb * ((H + ty - 1) / ty) < 2048) ty /= 2;
+  return ty;
+}
+
 hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s) {
   if (mx == 8 && my == 8 && mz == 4) return launch_pixel_t<8, 8, 4>(a, s);
   if (mx == 16 && my == 16 && mz == 8) return launch_pixel_t<16, 16, 8>(a, s);

@@ -62,6 +62,8 @@ bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy) {
   return mx == 16 && my == 16 && mz == 8 && nvx <= p16::NV1_MAX && nvy <= p16::NV1_MAX;
 }
 
+int p16_block_columns() { return p16::WAVES; }
+
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   const int xblocks = (a.W + p16::WAVES - 1) / p16::WAVES;
   const int yblocks = (a.H + a.TY - 1) / a.TY;

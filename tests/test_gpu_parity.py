@@ -193,6 +193,35 @@ def test_parity_paper_configuration(orc):
     check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
 
 
+def test_paper_scene_figure1_on_gpu():
+    """Fig. 1 of the paper on the GPU path alone, with the library's default
+    parameters for the 9x9x5 window (B = 3, m' = K): after settling the
+    clutter velocity is estimated near (1.625, 0.625) and the strongest
+    prediction-error response is the target, delayed by m'."""
+    T = 64
+    sc = scenes.paper_scene(7, T=T)
+    g = scenes.grid(-2, 2, 0.25)
+    res = run_gpu(sc.frames, (9, 9, 5), g, g)
+    # the occluding target corrupts the autocorrelation along its track (the
+    # smoother remembers it): judge the clutter velocity away from the track,
+    # in anchor coordinates (pixel + m'), and away from the zero-padded border
+    ys, xs = np.mgrid[0:64, 0:64]
+    keep = np.ones((64, 64), bool)
+    for t in range(T):
+        px, py = sc.targets[0, t]
+        keep &= np.hypot(xs - (px + 4), ys - (py + 4)) > 8
+    keep[:8, :] = False
+    keep[:, :8] = False
+    vx, vy = res["vxy"][-1, ..., 0], res["vxy"][-1, ..., 1]
+    near = (np.abs(vx - 1.625) <= 0.5) & (np.abs(vy - 0.625) <= 0.5)
+    assert keep.sum() > 2000 and near[keep].mean() >= 0.99, near[keep].mean()
+    out = np.abs(res["out"][-1, 8:, 8:])
+    yy, xx = np.unravel_index(np.argmax(out), out.shape)
+    tx, ty = sc.targets[0, T - 1 - 2]
+    assert abs(xx + 8 - 4 - tx) <= 3 and abs(yy + 8 - 4 - ty) <= 3
+    assert out.max() > 10 * out.std()
+
+
 @pytest.mark.parametrize("M,B,v", [((8, 8, 4), 3, (0.7, -1.3)), ((16, 16, 8), 6, (-2.3, 0.45)),
                                    ((16, 16, 8), 5, (1.5, -0.75)),
                                    ((9, 9, 5), 3, (1.625, 0.625))])
