@@ -61,6 +61,9 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p] + [ctypes.c_void_p] * 9
         L.orc_threads.restype = ctypes.c_int
+        L.orc_peak_vertex.restype = ctypes.c_double
+        L.orc_peak_vertex.argtypes = [ctypes.c_double] * 6
+        L.orc_refine.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
         _LIB = L
         del dp
     return _LIB
@@ -139,6 +142,20 @@ def _p(a):
 def dirichlet(W: int, w: float) -> float:
     """Eq. (3)."""
     return lib().orc_dirichlet(int(W), float(w))
+
+
+def peak_vertex(x0, r0, x1, r1, x2, r2) -> float:
+    """Vertex of the parabola through three points (velocity mode 3)."""
+    return lib().orc_peak_vertex(*(float(v) for v in (x0, r0, x1, r1, x2, r2)))
+
+
+def refine(cfg: Cfg, rsp: np.ndarray, best: int) -> tuple:
+    """Sub-grid velocity from the smoothed R of one anchor (velocity mode 3)."""
+    rsp = np.ascontiguousarray(rsp, np.float64)
+    vx, vy = ctypes.c_double(), ctypes.c_double()
+    c = cfg.c()
+    lib().orc_refine(ctypes.byref(c), rsp.ctypes.data, int(best), ctypes.byref(vx), ctypes.byref(vy))
+    return vx.value, vy.value
 
 
 def coeffs(cfg: Cfg, vx: float, vy: float) -> np.ndarray:
@@ -236,6 +253,8 @@ def pixel_series(cfg: Cfg, frames: np.ndarray, x: int, y: int, T: int | None = N
         if cfg.vmode == 2:
             key = (cfg.fvx, cfg.fvy)
             idx[t] = -1
+        elif cfg.vmode == 3:
+            key = refine(cfg, rs[t], idx[t])
         else:
             key = (cfg.gx[idx[t] % nvx], cfg.gy[idx[t] // nvx])
         if key not in cache:

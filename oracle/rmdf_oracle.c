@@ -229,6 +229,28 @@ double orc_background(const orc_cfg *c, const double complex *Hk, const double c
   return creal(acc);
 }
 
+double orc_peak_vertex(double x0, double r0, double x1, double r1, double x2, double r2) {
+  /* r(x) = r1 + b (x - x1) + a (x - x1)^2 through the three points; vertex at
+   * x1 - b / (2a).  With h0 = x1 - x0, h2 = x2 - x1:
+   *   r0 - r1 = -b h0 + a h0^2,  r2 - r1 = b h2 + a h2^2. */
+  const double h0 = x1 - x0, h2 = x2 - x1;
+  const double d0 = r0 - r1, d2 = r2 - r1;
+  const double a = (d0 * h2 + d2 * h0) / (h0 * h2 * (h0 + h2));
+  const double b = (d2 * h0 * h0 - d0 * h2 * h2) / (h0 * h2 * (h0 + h2));
+  if (a == 0.0) return x1;
+  return x1 - b / (2.0 * a);
+}
+
+void orc_refine(const orc_cfg *c, const double *rsp, int best, double *vx, double *vy) {
+  const int nvx = c->nvx, nvy = c->nvy, ix = best % nvx, iy = best / nvx;
+  *vx = c->gx[ix];
+  *vy = c->gy[iy];
+  if (ix > 0 && ix < nvx - 1)
+    *vx = orc_peak_vertex(c->gx[ix - 1], rsp[best - 1], c->gx[ix], rsp[best], c->gx[ix + 1], rsp[best + 1]);
+  if (iy > 0 && iy < nvy - 1)
+    *vy = orc_peak_vertex(c->gy[iy - 1], rsp[best - nvx], c->gy[iy], rsp[best], c->gy[iy + 1], rsp[best + nvx]);
+}
+
 static int cfg_ok(const orc_cfg *c) {
   if (c->H < 1 || c->W < 1) return 0;
   if (c->Mx < 2 || c->My < 2 || c->Mz < 2) return 0;
@@ -237,6 +259,11 @@ static int cfg_ok(const orc_cfg *c) {
   if (c->dx < 0 || c->dx >= c->Mx || c->dy < 0 || c->dy >= c->My || c->dt < 0 || c->dt >= c->Mz) return 0;
   if (!(c->alpha >= 0.0 && c->alpha < 1.0)) return 0;
   if (c->nvx < 1 || c->nvy < 1 || !c->gx || !c->gy) return 0;
+  if (c->vmode != 0 && c->vmode != 2 && c->vmode != 3) return 0;
+  if (c->vmode == 3) {
+    for (int i = 1; i < c->nvx; ++i) if (!(c->gx[i] > c->gx[i - 1])) return 0;
+    for (int i = 1; i < c->nvy; ++i) if (!(c->gy[i] > c->gy[i - 1])) return 0;
+  }
   return 1;
 }
 
@@ -318,6 +345,7 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
       double complex *w1 = malloc(sizeof(double complex) * N);
       double complex *w2 = malloc(sizeof(double complex) * N);
       double *R = malloc(sizeof(double) * nv);
+      double complex *Href = (c->vmode == 3) ? malloc(sizeof(double complex) * N) : NULL;
 #pragma omp for
       for (int y = 0; y < H; ++y)
         for (int x = 0; x < W; ++x) {
@@ -350,7 +378,11 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
           double vx, vy;
           const double complex *Hsel;
           if (c->vmode == 2) { vx = c->fvx; vy = c->fvy; Hsel = Hk + (size_t)nv * N; best = -1; }
-          else { vx = c->gx[best % c->nvx]; vy = c->gy[best / c->nvx]; Hsel = Hk + (size_t)best * N; }
+          else if (c->vmode == 3) {
+            orc_refine(c, rsp, best, &vx, &vy);
+            orc_coeffs(c, vx, vy, Href);
+            Hsel = Href;
+          } else { vx = c->gx[best % c->nvx]; vy = c->gy[best / c->nvx]; Hsel = Hk + (size_t)best * N; }
           if (vxy) { vxy[((size_t)t * HW + p) * 2] = vx; vxy[((size_t)t * HW + p) * 2 + 1] = vy; }
           if (idx) idx[(size_t)t * HW + p] = best;
 
@@ -360,7 +392,7 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
           double Id = (ts >= 0 && xs >= 0 && ys >= 0) ? img[(size_t)ts * HW + (size_t)ys * W + xs] : 0.0;
           if (out) out[(size_t)t * HW + p] = Id - Ihat;
         }
-      free(S); free(w1); free(w2); free(R);
+      free(S); free(w1); free(w2); free(R); free(Href);
     }
   }
   if (rs_last) memcpy(rs_last, rs, sizeof(double) * HW * nv);

@@ -38,7 +38,10 @@ typedef struct {
   int nvx, nvy;        /* candidate-velocity grid sizes                       */
   const double *gx;    /* nvx candidate x-velocities (pixels/frame)           */
   const double *gy;    /* nvy candidate y-velocities                          */
-  int vmode;           /* 0: argmax search; 2: fixed velocity (fvx, fvy)      */
+  int vmode;           /* 0: argmax search; 2: fixed velocity (fvx, fvy);
+                          3: argmax search, then the peak refined between
+                          grid points (orc_refine) and eq. (8) evaluated at
+                          the refined, continuous velocity                 */
   double fvx, fvy;
 } orc_cfg;
 
@@ -50,6 +53,20 @@ double orc_dirichlet(int Wn, double w);
  * after eq. 8).  Output Hk[(kx*My + ky)*Mz + kz], kx in [0,Mx) etc.
  * (8h) is read with Delta_z (the printed Delta_x is a typo). */
 void orc_coeffs(const orc_cfg *c, double vx, double vy, double complex *Hk);
+
+/* Abscissa of the vertex of the parabola through (x0, r0), (x1, r1), (x2, r2)
+ * (x0 < x1 < x2, r1 the largest); x1 when the three values are equal. */
+double orc_peak_vertex(double x0, double r0, double x1, double r1, double x2, double r2);
+
+/* Sub-grid velocity (velocity mode 3).  The paper obtains finer velocity
+ * resolution by evaluating R at finer, non-integer lags (Sec. 2, the flow
+ * paragraph); mode 3 instead interpolates between the grid lags: with the
+ * first maximum of the smoothed R at (ix, iy), each axis takes the vertex of
+ * the parabola through the peak and its two neighbours along that axis, the
+ * other index held fixed.  An axis whose peak is on the grid's edge keeps the
+ * grid value.  rsp holds nvy*nvx values, index iy*nvx + ix; grids strictly
+ * increasing. */
+void orc_refine(const orc_cfg *c, const double *rsp, int best, double *vx, double *vy);
 
 /* Observer of Sec. 1 for one spatial bin over T frames (integrator form).
  * s2[t] is the 2-D spectrum value fed in at frame t; a0 (Mz values, may be
@@ -70,7 +87,8 @@ double orc_background(const orc_cfg *c, const double complex *Hk,
 /* Whole pipeline over T frames (frames: T*H*W float32, row-major [t][y][x]).
  * Per frame t and anchor (x, y):
  *   out[t][y][x]  = I(t-dt, x-dx, y-dy) - Ihat      (zero outside the frame)
- *   vxy[t][y][x][2] = chosen velocity, idx[t][y][x] = iy*nvx + ix (-1 in vmode 2)
+ *   vxy[t][y][x][2] = chosen velocity, idx[t][y][x] = iy*nvx + ix (-1 in vmode 2;
+ *                     in vmode 3 the grid peak that was refined)
  * Optional (may be NULL):
  *   rs_last  H*W*nv   smoothed R after the last frame
  *   r_all    T*H*W*nv instantaneous R of every frame

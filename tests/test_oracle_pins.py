@@ -357,3 +357,82 @@ def test_subgrid_velocity_lands_in_cell(orc):
     vy = r["vxy"][-1, 15:, 15:, 1]
     ok = (vx >= 1.5) & (vx <= 2.0) & (vy >= 0.5) & (vy <= 1.0)
     assert ok.mean() >= 0.95
+
+
+# Velocity mode 3 (sub-grid refinement of the smoothed-R peak).  The vertex of
+# a parabola sampled at any three abscissae is the parabola's own vertex.
+@pytest.mark.parametrize("xs", [(-0.5, 0.0, 0.5), (1.0, 2.0, 3.0), (-1.0, -0.25, 1.5), (0.0, 0.1, 0.35)])
+def test_peak_vertex_recovers_a_parabola(orc, xs):
+    rng = np.random.default_rng(11)
+    x0, x1, x2 = xs
+    for _ in range(20):
+        # vertex between the midpoints, so the middle sample is the largest
+        xv = rng.uniform(0.5 * (x0 + x1), 0.5 * (x1 + x2))
+        a, c = -rng.uniform(0.1, 5.0), rng.normal()
+        r = [a * (x - xv) ** 2 + c for x in xs]
+        assert r[1] >= r[0] and r[1] >= r[2]
+        assert abs(orc.peak_vertex(x0, r[0], x1, r[1], x2, r[2]) - xv) <= 1e-9 * (1 + abs(xv))
+    assert orc.peak_vertex(x0, 2.0, x1, 2.0, x2, 2.0) == x1
+
+
+# On a separable quadratic bowl sampled on the grid (different curvature and
+# vertex per axis), refinement returns the bowl's centre; an axis whose peak is
+# on the grid's edge keeps the grid value.
+def test_refine_on_sampled_bowl(orc):
+    gx = scenes.grid(-2, 2, 0.5)
+    gy = np.array([-3.0, -1.0, 0.0, 0.5, 2.0, 4.0])
+    cfg = _cfg(orc, 4, 4, (8, 8, 4), gx=gx, gy=gy, vmode=3)
+    nvx = len(gx)
+    for cx, cy in [(0.3, 0.2), (-1.1, 1.3), (0.0, -0.6)]:
+        R = -(gx[None, :] - cx) ** 2 - 3.0 * (gy[:, None] - cy) ** 2
+        best = int(np.argmax(R))
+        vx, vy = orc.refine(cfg, R.ravel(), best)
+        assert abs(vx - cx) <= 1e-9 and abs(vy - cy) <= 1e-9, (cx, cy, vx, vy)
+    # peak on the x edge (centre beyond the grid): x keeps the grid value
+    R = -(gx[None, :] - 5.0) ** 2 - 3.0 * (gy[:, None] - 0.3) ** 2
+    best = int(np.argmax(R))
+    assert best % nvx == nvx - 1
+    vx, vy = orc.refine(cfg, R.ravel(), best)
+    assert vx == gx[-1] and abs(vy - 0.3) <= 1e-9
+    # unsorted grids are rejected in mode 3
+    bad = _cfg(orc, 8, 8, (8, 8, 4), gx=gx[::-1], gy=gy, vmode=3)
+    with pytest.raises(ValueError):
+        orc.run(bad, np.zeros((2, 8, 8), np.float32))
+
+
+# On clutter translating between grid points, the refined velocity is closer to
+# the truth than the grid search's, and the tuned filter leaves less residual.
+@pytest.mark.parametrize("v", [(1.3, -0.7), (0.6, 1.6)])
+def test_refined_velocity_beats_the_grid(orc, v):
+    from scipy import ndimage
+    rng = np.random.default_rng(0)
+    G = scenes.gaussian_field(rng, 128, 128, 10) + 100
+    H = W = 32
+    T = 12
+    ys, xs = np.mgrid[0:H, 0:W].astype(float)
+    fr = np.stack([ndimage.map_coordinates(G, [ys - v[1] * t, xs - v[0] * t], order=3, mode="grid-wrap")
+                   for t in range(T)]).astype(np.float32)
+    g = scenes.grid(-3, 3, 1.0)
+    res = {}
+    for vm in (0, 3):
+        r = orc.run(_cfg(orc, H, W, (8, 8, 4), gx=g, gy=g, vmode=vm), fr)
+        vv = r["vxy"][-1, 7:, 7:]
+        res[vm] = (np.hypot(vv[..., 0] - v[0], vv[..., 1] - v[1]).mean(),
+                   np.sqrt((r["out"][-1, 7:, 7:] ** 2).mean()), r["idx"][-1])
+    assert res[3][0] < 0.75 * res[0][0], res
+    assert res[3][1] < 0.85 * res[0][1], res
+    assert np.array_equal(res[0][2], res[3][2])      # the grid peak itself is the same
+
+
+# The direct per-pixel route agrees with the recursive route in mode 3 too.
+def test_pixel_series_matches_run_refined(orc):
+    sc = scenes.translate_scene(3, H=20, W=22, T=9, v=(1, -1), n_targets=1)
+    g = scenes.grid(-2, 2, 0.5)
+    cfg = _cfg(orc, 20, 22, (8, 8, 4), gx=g, gy=g, vmode=3)
+    r = orc.run(cfg, sc.frames, want_rs=True)
+    for (x, y) in [(21, 19), (10, 12)]:
+        p = orc.pixel_series(cfg, sc.frames, x, y)
+        for t in range(4, 9):
+            if p["idx"][t] == r["idx"][t, y, x]:
+                assert np.abs(p["vxy"][t] - r["vxy"][t, y, x]).max() <= 1e-7
+                assert abs(p["out"][t] - r["out"][t, y, x]) <= 1e-7 * 100
