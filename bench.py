@@ -222,6 +222,59 @@ def learned_leg(dev, sc, M, g, steps, warmup):
             "conf_threshold": 0.9}
 
 
+def refined_leg(dev, sc, M, g, steps, warmup):
+    """Velocity mode 3 (peak refined between grid points, coefficients at the
+    refined velocity) on the same frames: pixel-frames/s and pixel-kernel time,
+    PEF residual RMS and velocity RMSE against the true field for both modes
+    over the last 10 of the first 40 frames (away from targets and border)."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3526_amd import binding, learned
+    T, H, W = dev.shape
+    dx, dy, dt = M[0] // 2, M[1] // 2, M[2] // 2
+    tv = sc.velocity[np.clip(np.arange(H) - dy, 0, H - 1)][:, np.clip(np.arange(W) - dx, 0, W - 1)]
+    stats = {}
+    n_eval = min(40, T)
+    for mode in (binding.VEL_SEARCH, binding.VEL_REFINED):
+        f = binding.Filter(H, W, *M, g, g, velocity_mode=mode)
+        resid, rmse = [], []
+        for t in range(n_eval):
+            f.push_frame(dev[t])
+            if t >= n_eval - 10:
+                out = f.output().cpu().numpy()
+                vxy, _ = f.velocity()
+                vxy = vxy.cpu().numpy()
+                m = learned.valid_mask(H, W, sc.targets, t - dt, dx=dx, dy=dy)
+                resid.append(float(np.sqrt(np.mean(out[m].astype(np.float64) ** 2))))
+                rmse.append(float(np.sqrt(np.mean(np.sum((vxy[m] - tv[m]) ** 2, -1)))))
+        f.close()
+        stats[mode] = (float(np.mean(resid)), float(np.mean(rmse)))
+    f = binding.Filter(H, W, *M, g, g, velocity_mode=binding.VEL_REFINED)
+    for i in range(warmup):
+        f.push_frame(dev[i % T])
+    torch.cuda.synchronize()
+    f.set_timing(True)
+    f.kernel_time(0)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(steps):
+        f.push_frame(dev[(warmup + i) % T])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k = f.kernel_time(0)
+    f.set_timing(False)
+    f.close()
+    ps, pr = stats[binding.VEL_SEARCH], stats[binding.VEL_REFINED]
+    return {"value": steps * H * W / (ms / 1e3), "unit": "pixel-frames/s", "ms_per_step": ms / steps,
+            "kernel_ms": k[0] / max(k[1], 1),
+            "residual_rms": pr[0], "plain_residual_rms": ps[0], "residual_ratio": pr[0] / ps[0],
+            "velocity_rmse": pr[1], "plain_velocity_rmse": ps[1]}
+
+
 def cpu_baseline(frames, wl, g, budget_frames=8, crop=64):
     """The FP64 oracle, as it is, on a bounded sample: a crop x crop window of
     the same frames for budget_frames frames, on all host cores."""
@@ -251,6 +304,7 @@ def main():
     ap.add_argument("--kernel-variant", type=int, default=0, help="0 auto, 1 generic, 2 wave-per-anchor")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-velocity leg")
+    ap.add_argument("--no-refined", action="store_true", help="skip the refined-velocity leg")
     ap.add_argument("--batch24", action="store_true",
                     help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -350,6 +404,10 @@ def main():
     if lr is not None:
         lr["vs_plain"] = lr["value"] / value
         res["learned"] = lr
+    if not args.no_refined:
+        rf = refined_leg(dev, sc, M, g, min(args.steps, 200), args.warmup)
+        rf["vs_plain"] = rf["value"] / value
+        res["refined"] = rf
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(frames, wl, g)
     print(json.dumps(res), flush=True)

@@ -53,7 +53,17 @@ typedef enum {
 typedef enum {
   RMDF_VEL_SEARCH = 0,      /* argmax of the smoothed autocorrelation (Sec. 2) */
   RMDF_VEL_LEARNED = 1,     /* learned surrogate, search where confidence low  */
-  RMDF_VEL_FIXED = 2        /* one velocity for every pixel (fixed_vx, fixed_vy) */
+  RMDF_VEL_FIXED = 2,       /* one velocity for every pixel (fixed_vx, fixed_vy) */
+  RMDF_VEL_REFINED = 3      /* search, then the peak refined between grid points:
+                               per axis, the vertex of the parabola through the
+                               first maximum of the smoothed R and its two grid
+                               neighbours (an edge peak keeps the grid value);
+                               eq. (8) is evaluated at that continuous velocity
+                               for each anchor.  The grids must be strictly
+                               increasing.  rmdf_velocity returns the refined
+                               velocity and the grid peak's index.  (The paper
+                               gets finer resolution from finer lag grids,
+                               Sec. 2; this interpolates between them.)      */
 } rmdf_velocity_mode;
 
 typedef struct {
@@ -195,7 +205,8 @@ rmdf_status rmdf_tile_rows(const rmdf_ctx *ctx, int *tile_rows);
  * s in {1, 2, 4}; the coefficients then factor into a spatial phase per
  * (kx, ky) and a 16 s x Kt table of the temporal part, held in LDS.
  * *lattice_q = 0: a per-candidate table in device memory is read instead
- * (any other grid, or the generic kernel). */
+ * (any other grid, or the generic kernel), or, in RMDF_VEL_REFINED mode, the
+ * coefficients are evaluated per anchor at the refined velocity. */
 rmdf_status rmdf_coeff_lattice(const rmdf_ctx *ctx, int *lattice_q);
 
 /* Bytes of device memory the context holds. */

@@ -19,7 +19,7 @@ SO_PATH = os.path.join(_HERE, "librmdf.so")
 _LIB = None
 
 RMDF_OK, RMDF_E_INVAL, RMDF_E_NOMEM, RMDF_E_DEVICE, RMDF_E_STATE, RMDF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-VEL_SEARCH, VEL_LEARNED, VEL_FIXED = 0, 1, 2
+VEL_SEARCH, VEL_LEARNED, VEL_FIXED, VEL_REFINED = 0, 1, 2, 3
 
 _STATUS = {0: "RMDF_OK", -1: "RMDF_E_INVAL", -2: "RMDF_E_NOMEM", -3: "RMDF_E_DEVICE",
            -4: "RMDF_E_STATE", -5: "RMDF_E_UNSUPPORTED"}

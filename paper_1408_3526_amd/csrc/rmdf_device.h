@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rmdf_kernels.h"
+#include "rmdf_refine.h"
 
 namespace rmdf {
 
@@ -128,6 +129,27 @@ struct Shape {
 // (value, index) argmax with the first (lowest-index) maximum winning.
 static __device__ __forceinline__ void amax_merge(float& v, int& i, float v2, int i2) {
   if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+// Eq. (8) at bin (kx, ky, kz) for a continuous velocity (the spatial Dirichlet
+// factors select kx' = kx, ky' = ky at the bins), times sqrt(Mz) since the
+// state holds S / sqrt(Mz):
+//   D_Mz(kz/Mz + phi) / sqrt(Mx My) * exp(j pi [-2(kx m'x/Mx + ky m'y/My)
+//   + 2 phi (m't - Dz) - 2 kz Dz/Mz]),  phi = vx kx/Mx + vy ky/My.
+template <int MX, int MY, int MZ>
+static __device__ __forceinline__ float2 coeff_at(int kx, int ky, int kz, float vx, float vy, int dx, int dy, int dt) {
+  const float Dz = 0.5f * (MZ - 1);
+  const float phi = vx * kx * (1.0f / MX) + vy * ky * (1.0f / MY);
+  const float w = kz * (1.0f / MZ) + phi;
+  const float rw = rintf(w);
+  float D;
+  if (fabsf(w - rw) < 1e-5f) D = (((int)rw * (MZ - 1)) & 1) ? -1.f : 1.f;
+  else D = sinpif(MZ * w) / (MZ * sinpif(w));
+  const float ph = -2.f * (kx * (float)dx / MX + ky * (float)dy / MY) + 2.f * phi * (dt - Dz) - 2.f * kz * Dz / MZ;
+  float sn, cs;
+  sincospif(ph, &sn, &cs);
+  const float g = D * (1.0f / sqrtf((float)(MX * MY)));
+  return make_float2(g * cs, g * sn);
 }
 
 // One work tile: PPB adjacent anchor columns starting at xb*PPB, rows
@@ -364,16 +386,38 @@ static __device__ void pixel_tile(const PixArgs& a, const float* ring_delayed, i
     }
     const int istar = (bi < nv) ? bi : 0;   // no finite candidate: fall back to index 0
 
+    // ---- velocity mode 3: refine the peak between grid points, from the
+    // smoothed R this row has just stored (the barrier makes the workgroup's
+    // global stores visible to all of its threads)
+    float2 vref = make_float2(0.f, 0.f);
+    if (a.vmode == 3) {
+      __syncthreads();
+      if (px_ok) {
+        const float* rp = a.rsm + pix * nv;
+        vref = refine_peak(a.gx, a.gy, nvx, nvy, istar, rp[istar], [&](int w) { return rp[w]; });
+      }
+    }
+
     // ---- background estimate (eq. 4) with the coefficients of the chosen
-    // velocity (eq. 8 at the bins; Hermitian weights folded into the table)
+    // velocity (eq. 8 at the bins; Hermitian weights folded into the table, or
+    // evaluated here for the refined velocity)
     const int hsel = (a.vmode == 2) ? nv : istar;
     float acc = 0.f;
     if (col_ok && p <= a.bx) {
       const int kyc = (2 * ky <= MY) ? ky : ky - MY;
       if (kyc >= -a.by && kyc <= a.by) {
-        const float2* h = a.htab + (((size_t)hsel * (a.bx + 1) + p) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+        if (a.vmode == 3) {
+          const float wgt = (p == 0) ? 1.f : 2.f;
 #pragma unroll
-        for (int kz = 0; kz < MZ; ++kz) acc += h[kz].x * X[kz].x - h[kz].y * X[kz].y;
+          for (int kz = 0; kz < MZ; ++kz) {
+            const float2 h = coeff_at<MX, MY, MZ>(p, kyc, kz, vref.x, vref.y, a.dx, a.dy, a.dt);
+            acc += wgt * (h.x * X[kz].x - h.y * X[kz].y);
+          }
+        } else {
+          const float2* h = a.htab + (((size_t)hsel * (a.bx + 1) + p) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+#pragma unroll
+          for (int kz = 0; kz < MZ; ++kz) acc += h[kz].x * X[kz].x - h[kz].y * X[kz].y;
+        }
       }
     }
 #pragma unroll
@@ -395,7 +439,7 @@ static __device__ void pixel_tile(const PixArgs& a, const float* ring_delayed, i
         a.vxy[pix] = make_float2(a.fvx, a.fvy);
         a.vidx[pix] = -1;
       } else {
-        a.vxy[pix] = make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
+        a.vxy[pix] = (a.vmode == 3) ? vref : make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
         a.vidx[pix] = istar;
       }
     }

@@ -342,8 +342,16 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   if (dx >= Kx || dy >= Ky || dt >= Kt) return fail(nullptr, RMDF_E_INVAL, "delay m' must be < M");
   const float alpha = p.alpha < 0.f ? std::exp(-0.1f) : p.alpha;
   if (!(alpha >= 0.f && alpha < 1.f)) return fail(nullptr, RMDF_E_INVAL, "alpha must be in [0, 1)");
-  if (p.velocity_mode < RMDF_VEL_SEARCH || p.velocity_mode > RMDF_VEL_FIXED)
+  if (p.velocity_mode < RMDF_VEL_SEARCH || p.velocity_mode > RMDF_VEL_REFINED)
     return fail(nullptr, RMDF_E_INVAL, "unknown velocity mode");
+  if (p.velocity_mode == RMDF_VEL_REFINED) {
+    for (int i = 1; i < nvx; ++i)
+      if (!(vgrid_x[i] > vgrid_x[i - 1])) return fail(nullptr, RMDF_E_INVAL, "refined velocity needs strictly increasing grids");
+    for (int i = 1; i < nvy; ++i)
+      if (!(vgrid_y[i] > vgrid_y[i - 1])) return fail(nullptr, RMDF_E_INVAL, "refined velocity needs strictly increasing grids");
+    if (p.write_features)
+      return fail(nullptr, RMDF_E_UNSUPPORTED, "write_features needs velocity mode 0");
+  }
   if (p.velocity_mode == RMDF_VEL_FIXED && !(std::isfinite(p.fixed_vx) && std::isfinite(p.fixed_vy)))
     return fail(nullptr, RMDF_E_INVAL, "fixed velocity must be finite");
   if (p.tile_rows < 0) return fail(nullptr, RMDF_E_INVAL, "tile_rows must be >= 0");
@@ -455,7 +463,7 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   rmdf::PixArgs a = rmdf_internal_pixargs(c);
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
   if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
-  const int mode = (c->vmode == RMDF_VEL_LEARNED) ? 2 : (c->write_features ? 1 : 0);
+  const int mode = (c->vmode == RMDF_VEL_LEARNED) ? 2 : (c->vmode == RMDF_VEL_REFINED) ? 3 : (c->write_features ? 1 : 0);
   timed_begin(c, 0, &ev);
   e = (c->variant == 2) ? rmdf::launch_pixel16(a, mode, c->stream)
                         : rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
@@ -647,7 +655,7 @@ rmdf_status rmdf_tile_rows(const rmdf_ctx* c, int* tile_rows) {
 
 rmdf_status rmdf_coeff_lattice(const rmdf_ctx* c, int* lattice_q) {
   if (!c || !lattice_q) return RMDF_E_INVAL;
-  *lattice_q = (c->variant == 2) ? c->lat_q : 0;
+  *lattice_q = (c->variant == 2 && c->vmode != RMDF_VEL_REFINED) ? c->lat_q : 0;
   return RMDF_OK;
 }
 

@@ -15,7 +15,7 @@ struct PixArgs {
   int H, W, TY;                // frame size, rows per work tile
   int nvx, nvy, nv;            // candidate grid
   int bx, by, dx, dy;          // half-bandwidth, spatial output delay
-  int vmode;                   // 0 search, 2 fixed velocity
+  int vmode;                   // 0 search, 2 fixed velocity, 3 search refined between grid points
   float alpha, inv_sqrt_my;
   float fvx, fvy;
   const float2* rs;            // row spectra [H][W][planes]
@@ -62,6 +62,8 @@ hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, cons
                            bool layout16, hipStream_t s);
 bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
 int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anchor kernel
+// mode: 0 search (or fixed velocity), 1 search + learned features, 2 learned
+// first pass, 3 search refined between grid points
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 // list: [1 + H*W] ints of scratch (count, then the confident anchors)
 hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include "rmdf_kernels.h"
+#include "rmdf_refine.h"
 
 namespace rmdf {
 namespace p16 {
@@ -178,11 +179,53 @@ static __device__ __forceinline__ unsigned short to_bf16(float f) {
   return (unsigned short)(u >> 16);
 }
 
+// cos(m pi / 8) and sin(m pi / 8) for integer m.
+__device__ constexpr float cos_pi8(int m) {
+  constexpr float t[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+                           0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f,
+                           -1.0f, -0.92387953251128674f, -0.70710678118654752f, -0.38268343236508977f,
+                           0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f};
+  return t[((m % 16) + 16) % 16];
+}
+__device__ constexpr float sin_pi8(int m) { return cos_pi8(m - 4); }
+
+// Background estimate of eq. (4) over one lane's plane (kx, ky centred, all
+// kz) at a continuous velocity (mode 3).  The coefficient of eq. (8) at the
+// bin, times sqrt(Mz) (X = S / sqrt(Mz)), is
+//   D_8(kz/8 + phi) / 16 * exp(j pi [ph0 - 7 kz / 8]),
+//   phi = (vx kx + vy ky) / 16,  ph0 = -2 (kx m'x + ky m'y) / 16 + 2 phi (m't - 7/2),
+// Hermitian weight 2 for kx > 0.  The Dirichlet kernel of order 8 is the mean
+// of cos((2i+1) pi w), i = 0..3, i.e. with c = cos(pi w) the Chebyshev sum
+//   D_8(w) = c (((16 c^2 - 24) c^2 + 10) c^2 - 1),
+// and cos(pi (kz/8 + phi)) comes from one sine/cosine pair of phi.
+static __device__ __forceinline__ float pef_plane16(const float2* X, int kx, int kyc, float vx, float vy, int dx,
+                                                    int dy, int dt) {
+  const float phi = (vx * kx + vy * kyc) * (1.0f / 16.0f);
+  float sp, cp;
+  sincospif(phi, &sp, &cp);
+  const float ph0 = -2.f * (float)(kx * dx + kyc * dy) * (1.0f / 16.0f) + 2.f * phi * ((float)dt - 3.5f);
+  float s0, c0;
+  sincospif(ph0, &s0, &c0);
+  float acc = 0.f;
+#pragma unroll
+  for (int kz = 0; kz < MZ; ++kz) {
+    const float c = cos_pi8(kz) * cp - sin_pi8(kz) * sp;
+    const float c2 = c * c;
+    const float D = c * (((16.f * c2 - 24.f) * c2 + 10.f) * c2 - 1.f);
+    // exp(j pi ph0) exp(-j 7 pi kz / 8)
+    const float tc = cos_pi8(7 * kz), ts = -sin_pi8(7 * kz);
+    const float er = c0 * tc - s0 * ts, ei = c0 * ts + s0 * tc;
+    acc += D * (er * X[kz].x - ei * X[kz].y);
+  }
+  return acc * ((kx == 0) ? (1.0f / 16.0f) : (2.0f / 16.0f));
+}
+
 // MODE: 0 plain search; 1 plain search that also writes the learned model's
 // input features; 2 learned mode, first pass: features, and the complete
 // fallback result (instantaneous search, i.e. no smoothed-R state, its
 // background estimate and output), which finish16 overwrites where the
-// network is confident.
+// network is confident; 3 plain search with the peak refined between grid
+// points and the background coefficients evaluated at the refined velocity.
 template <int MODE>
 static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   lds_v2* s_all = (lds_v2*)(smem);
@@ -408,7 +451,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       QA = hann_x_power<0, false>(s_b, ky, pA, HA, PA);
     }
     QB = hann_x_power<0, false>(s_b, ky, pB, HB, PB);
-    if (MODE >= 1) {
+    if (MODE == 1 || MODE == 2) {
       // learned-model input: x = ln(P + eps) - mean over all Mx*My*Mz bins,
       // eps = 1e-6 max P; stored for kx = 0..8 ([kx][ky][kz], BF16); bins
       // with kx = 1..7 stand for their conjugate partner too (weight 2)
@@ -490,6 +533,9 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     // smoothing and argmax
     float bv = -INFINITY;
     int bi = 0x7fffffff;
+    float smv[MODE == 3 ? NC_IT : 1];    // mode 3: this lane's smoothed R, for the peak's neighbours
+#pragma unroll
+    for (int j = 0; j < (MODE == 3 ? NC_IT : 1); ++j) smv[j] = 0.f;
     if (actC) {
       float cC[7], sC[7], c8C;
       {
@@ -514,6 +560,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
             sm = (1.f - a.alpha) * rv + a.alpha * rprev[j];
             a.rsm[pix * nv + w] = sm;
           }
+          if (MODE == 3) smv[j] = sm;
           amax_merge(bv, bi, sm, w);
         }
         __builtin_amdgcn_sched_barrier(0);   // keep one iteration's LDS reads in flight at a time
@@ -528,11 +575,34 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     const int istar = (bi < nv) ? bi : 0;
     if (MODE == 2 && lane == 0) a.fidx[pix] = istar;
 
+    // ---- mode 3: the peak refined between grid points; R at (ix, iy) is held
+    // by lane (iy mod 3) nvx + ix in its slot iy / 3
+    float2 vref = f2(0.f, 0.f);
+    if (MODE == 3) {
+      const int best = __builtin_amdgcn_readfirstlane(istar);
+      auto rv = [&](int w) -> float {
+        const int iyn = w / nvx, ixn = w - iyn * nvx;
+        const int jn = iyn / 3, src = (iyn - 3 * jn) * nvx + ixn;
+        float v = 0.f;
+#pragma unroll
+        for (int j = 0; j < (MODE == 3 ? NC_IT : 1); ++j)
+          if (j == jn) v = smv[j];
+        return __shfl(v, src, 64);
+      };
+      const float rbest = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bv)));
+      vref = refine_peak(a.gx, a.gy, nvx, nvy, best, rbest, rv);
+    }
+
     // ---- background estimate with the chosen velocity's coefficients (the
     // posterior state is still in registers)
     const int hsel = __builtin_amdgcn_readfirstlane((a.vmode == 2) ? nv : istar);
     float acc = 0.f;
-    if (lattice) {
+    if (MODE == 3) {
+      if (kyc >= -a.by && kyc <= a.by) {
+        if (pA <= a.bx) acc = pef_plane16(XA, pA, kyc, vref.x, vref.y, a.dx, a.dy, a.dt);
+        if (pB <= a.bx) acc += pef_plane16(XB, pB, kyc, vref.x, vref.y, a.dx, a.dy, a.dt);
+      }
+    } else if (lattice) {
       // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
       const int nq = a.latq[hsel];
       const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
@@ -573,7 +643,7 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
         a.vxy[pix] = make_float2(a.fvx, a.fvy);
         a.vidx[pix] = -1;
       } else {
-        a.vxy[pix] = make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
+        a.vxy[pix] = (MODE == 3) ? vref : make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
         a.vidx[pix] = istar;
       }
     }
