@@ -81,6 +81,7 @@ class Scene:
     velocity: np.ndarray        # [H, W, 2] true background velocity (vx, vy), px/frame
     targets: np.ndarray         # [n, T, 2] target centres (x, y) per frame
     band_mask: np.ndarray | None = None   # [T, H, W] bool, pixels covered by the band
+    target_snr: np.ndarray | None = None  # [n] target amplitude / noise sigma, where defined
 
 
 def translate_scene(seed: int, H: int = 64, W: int = 64, T: int = 32,
@@ -203,7 +204,7 @@ def flow_scene(seed: int, H: int = 512, W: int = 640, T: int = 200, n_targets: i
         frames[t] = img.astype(np.float32)
     if band:
         label[mask_all[-1]] = bv
-    return Scene(frames, label, tg, mask_all)
+    return Scene(frames, label, tg, mask_all, amps / noise_sigma)
 
 
 def paper_scene(seed: int = 7, H: int = 64, W: int = 64, T: int = 64,
