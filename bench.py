@@ -275,6 +275,71 @@ def refined_leg(dev, sc, M, g, steps, warmup):
             "velocity_rmse": pr[1], "plain_velocity_rmse": ps[1]}
 
 
+def detection_leg(dev, sc, M, g, guard=2, train=4, ks=(3.0, 3.5, 4.0, 5.0)):
+    """Detection stage after the filter: two-sided CA-CFAR (rmdf_cfar) on the
+    prediction error of the last 10 of the first 40 frames, and, for
+    comparison, on the raw input frames, at several thresholds k (points of
+    the Pd/Pfa curve).  A target counts as detected when a detection lies
+    within 2 px of it; detections farther than 4 px from every target count as
+    false alarms (15 px away from the frame border).  Pd per target SNR bin,
+    false alarms per pixel, and the CFAR kernel's time per frame."""
+    import numpy as np
+    import torch
+
+    from paper_1408_3526_amd import binding
+    if sc.target_snr is None:
+        return None
+    T, H, W = dev.shape
+    dx, dy, dt = M[0] // 2, M[1] // 2, M[2] // 2
+    n_eval = min(40, T)
+    f = binding.Filter(H, W, *M, g, g)
+    ys, xs = np.mgrid[0:H, 0:W]
+    bins = [(2, 4), (4, 6), (6, 8.01)]
+    snr = sc.target_snr
+    cnt = {(n, k): [np.zeros(len(bins)), np.zeros(len(bins)), 0, 0] for n in ("pef", "raw") for k in ks}
+    for t in range(n_eval):
+        f.push_frame(dev[t])
+        if t < n_eval - 10:
+            continue
+        t_out = t - dt
+        for name, img, ox, oy in (("pef", f.output(), dx, dy), ("raw", dev[t_out].contiguous(), 0, 0)):
+            near = np.zeros((H, W), bool)
+            disc = []
+            for i in range(sc.targets.shape[0]):
+                d2 = (xs - sc.targets[i, t_out, 0] - ox) ** 2 + (ys - sc.targets[i, t_out, 1] - oy) ** 2
+                near |= d2 <= 16.0
+                disc.append(d2 <= 4.0)
+            valid = ~near & (xs >= 15) & (ys >= 15) & (xs < W - 15) & (ys < H - 15)
+            for k in ks:
+                det = binding.cfar(img, guard, train, k).cpu().numpy().astype(bool)
+                c = cnt[(name, k)]
+                for i in range(len(disc)):
+                    j = next(j for j, (lo, hi) in enumerate(bins) if lo <= snr[i] < hi)
+                    c[0][j] += bool(det[disc[i]].any())
+                    c[1][j] += 1
+                c[2] += int(det[valid].sum())
+                c[3] += int(valid.sum())
+    f.close()
+    out = dev[n_eval - 1].contiguous()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(5):
+        binding.cfar(out, guard, train, ks[0])
+    e0.record(stream)
+    for _ in range(50):
+        binding.cfar(out, guard, train, ks[0])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    res = {"guard": guard, "train": train, "cfar_ms": e0.elapsed_time(e1) / 50,
+           "targets_by_snr": {"%g-%g" % (lo, min(hi, 8)): int(n) for (lo, hi), n in zip(bins, cnt[("pef", ks[0])][1])}}
+    for name in ("pef", "raw"):
+        res[name] = [{"k": k, "pfa": cnt[(name, k)][2] / max(cnt[(name, k)][3], 1),
+                      "pd_by_snr": {"%g-%g" % (lo, min(hi, 8)): float(h / n) if n else None
+                                    for (lo, hi), h, n in zip(bins, cnt[(name, k)][0], cnt[(name, k)][1])}}
+                     for k in ks]
+    return res
+
+
 def cpu_baseline(frames, wl, g, budget_frames=8, crop=64):
     """The FP64 oracle, as it is, on a bounded sample: a crop x crop window of
     the same frames for budget_frames frames, on all host cores."""
@@ -305,6 +370,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-velocity leg")
     ap.add_argument("--no-refined", action="store_true", help="skip the refined-velocity leg")
+    ap.add_argument("--no-detection", action="store_true", help="skip the CFAR detection leg")
     ap.add_argument("--batch24", action="store_true",
                     help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -408,6 +474,10 @@ def main():
         rf = refined_leg(dev, sc, M, g, min(args.steps, 200), args.warmup)
         rf["vs_plain"] = rf["value"] / value
         res["refined"] = rf
+    if not args.no_detection:
+        dl = detection_leg(dev, sc, M, g)
+        if dl is not None:
+            res["detection"] = dl
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(frames, wl, g)
     print(json.dumps(res), flush=True)

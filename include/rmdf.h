@@ -209,6 +209,21 @@ rmdf_status rmdf_tile_rows(const rmdf_ctx *ctx, int *tile_rows);
  * coefficients are evaluated per anchor at the refined velocity. */
 rmdf_status rmdf_coeff_lattice(const rmdf_ctx *ctx, int *lattice_q);
 
+/* Detection stage after the filter (the paper hands the prediction error to a
+ * threshold and a tracker, Sec. 1, without fixing the detector): two-sided
+ * cell-averaging CFAR on an H x W FP32 device image x_dev (row-major, e.g.
+ * what rmdf_output wrote).  Per pixel, the training cells are the in-frame
+ * pixels within Chebyshev distance guard + train that lie outside the guard
+ * square (which holds the pixel itself); mu = their mean, sigma^2 = the mean
+ * of their squares minus mu^2 (FP32), and det_dev[p] = 1 where there is at
+ * least one training cell and |x - mu| > k sigma, else 0 (H*W bytes, device).
+ * level_dev: H*W sigma values (device), or NULL.  guard >= 0, train >= 1,
+ * guard + train <= 16, k finite and >= 0; otherwise RMDF_E_INVAL with the
+ * message in rmdf_last_error(NULL).  Buffers are the caller's; the call is
+ * enqueued on `stream` (NULL: the default stream) and allocates nothing. */
+rmdf_status rmdf_cfar(const float *x_dev, int H, int W, int guard, int train, float k,
+                      unsigned char *det_dev, float *level_dev, void *stream);
+
 /* Bytes of device memory the context holds. */
 rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);
 

@@ -59,6 +59,7 @@ _SIGS = {
     "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_coeff_lattice": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_tile_rows": (_I, [_VP, ctypes.POINTER(_I)]),
+    "rmdf_cfar": (_I, [_VP, _I, _I, _I, _I, ctypes.c_float, _VP, _VP, _VP]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
     "rmdf_mlp_set_weights": (_I, [_VP, _VP, _SZ]),
@@ -485,3 +486,17 @@ def mlp_adam(p, g, m, v, p_bf16, lr, step, b1=0.9, b2=0.999, eps=1e-8):
 
 def mlp_to_bf16(inp, out):
     _check(lib().rmdf_mlp_to_bf16(inp.data_ptr(), out.data_ptr(), inp.numel(), ctypes.c_void_p(_stream_handle())))
+
+
+def cfar(x, guard: int, train: int, k: float, want_level: bool = False):
+    """Two-sided cell-averaging CFAR (rmdf_cfar) on a [H, W] float32 CUDA
+    tensor, on torch's current stream.  Returns the detections (uint8, 0/1)
+    and, if asked, the per-pixel sigma estimate."""
+    import torch
+    H, W = x.shape
+    xp = _dev_ptr(x, torch.float32, H * W, "image")
+    det = torch.empty((H, W), dtype=torch.uint8, device=x.device)
+    lev = torch.empty((H, W), dtype=torch.float32, device=x.device) if want_level else None
+    _check(lib().rmdf_cfar(xp, int(H), int(W), int(guard), int(train), float(k), det.data_ptr(), _p(lev),
+                           ctypes.c_void_p(_stream_handle())))
+    return (det, lev) if want_level else det
