@@ -275,6 +275,51 @@ def refined_leg(dev, sc, M, g, steps, warmup):
             "velocity_rmse": pr[1], "plain_velocity_rmse": ps[1]}
 
 
+def ring_bytes_per_pixel_frame(M, nv):
+    """Bytes per pixel and frame with the temporal ring: Mz - 1 stored 2-D
+    spectra read and one written (Mx*My reals each, FP32), the smoothed
+    autocorrelation read + write, and the same 24 bytes of frame, delayed
+    frame, output, velocity and index."""
+    Mx, My, Mz = M
+    return 4 * Mx * My * Mz + 2 * 4 * nv + 4 + 4 + 4 + 8 + 4
+
+
+def ring_leg(dev, M, g, steps, warmup):
+    """The temporal-ring variant (the temporal DFT taken directly over the last
+    Mz 2-D spectra instead of the observer) on the same frames: pixel-frames/s
+    and its pixel kernel's time against its own algorithmic bytes."""
+    import torch
+
+    from paper_1408_3526_amd import binding
+    if tuple(M) != (16, 16, 8):
+        return None
+    T, H, W = dev.shape
+    f = binding.Filter(H, W, *M, g, g, temporal=binding.TEMPORAL_RING)
+    for i in range(warmup):
+        f.push_frame(dev[i % T])
+    torch.cuda.synchronize()
+    f.set_timing(True)
+    f.kernel_time(0)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for i in range(steps):
+        f.push_frame(dev[(warmup + i) % T])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    k = f.kernel_time(0)
+    f.set_timing(False)
+    f.close()
+    kms = k[0] / max(k[1], 1)
+    bpp = ring_bytes_per_pixel_frame(M, len(g) ** 2)
+    ach = bpp * H * W / (kms / 1e3) / 1e9
+    return {"value": steps * H * W / (ms / 1e3), "unit": "pixel-frames/s", "ms_per_step": ms / steps,
+            "kernel_ms": kms, "algorithmic_bytes_per_pixel_frame": bpp, "achieved_GBps": ach,
+            "frac": ach / HBM_PEAK_GBS}
+
+
 def detection_leg(dev, sc, M, g, guard=2, train=4, ks=(3.0, 3.5, 4.0, 5.0)):
     """Detection stage after the filter: two-sided CA-CFAR (rmdf_cfar) on the
     prediction error of the last 10 of the first 40 frames, and, for
@@ -371,6 +416,7 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-velocity leg")
     ap.add_argument("--no-refined", action="store_true", help="skip the refined-velocity leg")
     ap.add_argument("--no-detection", action="store_true", help="skip the CFAR detection leg")
+    ap.add_argument("--no-ring", action="store_true", help="skip the temporal-ring variant leg")
     ap.add_argument("--batch24", action="store_true",
                     help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -474,6 +520,11 @@ def main():
         rf = refined_leg(dev, sc, M, g, min(args.steps, 200), args.warmup)
         rf["vs_plain"] = rf["value"] / value
         res["refined"] = rf
+    if not args.no_ring:
+        rg = ring_leg(dev, M, g, args.steps, args.warmup)
+        if rg is not None:
+            rg["vs_plain"] = rg["value"] / value
+            res["temporal_ring"] = rg
     if not args.no_detection:
         dl = detection_leg(dev, sc, M, g)
         if dl is not None:

@@ -85,7 +85,19 @@ typedef struct {
                                (16x16x8, at most 21 candidates per axis)       */
   int write_features;       /* search mode that also writes the learned model's
                                input features each frame (rmdf_features)       */
+  int temporal;             /* temporal part of the local spectrum:
+                               RMDF_TEMPORAL_OBSERVER (0, default): the deadbeat
+                               observer of Sec. 1, its Mz-bin state updated in
+                               place; RMDF_TEMPORAL_RING (1): a ring of the
+                               last Mz 2-D spectra per pixel and the Mz-point
+                               temporal DFT taken directly each frame (the same
+                               spectrum; the non-recursive comparison point of
+                               Sec. 5 applied to time only).  The ring needs the
+                               16x16x8 wave-per-anchor kernel and the search or
+                               fixed velocity mode; single contexts only.     */
 } rmdf_params;
+
+enum { RMDF_TEMPORAL_OBSERVER = 0, RMDF_TEMPORAL_RING = 1 };
 
 /* Fill *p with the defaults above (the -1 / negative markers). */
 void rmdf_params_default(rmdf_params *p);

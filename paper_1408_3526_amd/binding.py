@@ -20,6 +20,7 @@ _LIB = None
 
 RMDF_OK, RMDF_E_INVAL, RMDF_E_NOMEM, RMDF_E_DEVICE, RMDF_E_STATE, RMDF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 VEL_SEARCH, VEL_LEARNED, VEL_FIXED, VEL_REFINED = 0, 1, 2, 3
+TEMPORAL_OBSERVER, TEMPORAL_RING = 0, 1
 
 _STATUS = {0: "RMDF_OK", -1: "RMDF_E_INVAL", -2: "RMDF_E_NOMEM", -3: "RMDF_E_DEVICE",
            -4: "RMDF_E_STATE", -5: "RMDF_E_UNSUPPORTED"}
@@ -37,7 +38,7 @@ class rmdf_params(ctypes.Structure):
                 ("alpha", ctypes.c_float), ("velocity_mode", ctypes.c_int),
                 ("fixed_vx", ctypes.c_float), ("fixed_vy", ctypes.c_float),
                 ("conf_threshold", ctypes.c_float), ("tile_rows", ctypes.c_int),
-                ("kernel_variant", ctypes.c_int), ("write_features", ctypes.c_int)]
+                ("kernel_variant", ctypes.c_int), ("write_features", ctypes.c_int), ("temporal", ctypes.c_int)]
 
 
 # C signatures: name -> (restype, argtypes)
@@ -187,7 +188,8 @@ class Filter:
 
     def __init__(self, H, W, Kx, Ky, Kt, vgrid_x, vgrid_y, *, Bx=-1, By=-1, delay=(-1, -1, -1),
                  alpha=-1.0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0), conf_threshold=0.9,
-                 tile_rows=0, kernel_variant=0, write_features=False, stream=None, use_torch_stream=True):
+                 tile_rows=0, kernel_variant=0, write_features=False, temporal=TEMPORAL_OBSERVER, stream=None,
+                 use_torch_stream=True):
         import torch
         p = rmdf_params_default()
         p.Bx, p.By = int(Bx), int(By)
@@ -199,6 +201,7 @@ class Filter:
         p.tile_rows = int(tile_rows)
         p.kernel_variant = int(kernel_variant)
         p.write_features = int(bool(write_features))
+        p.temporal = int(temporal)
         if stream is None and use_torch_stream:
             stream = torch.cuda.current_stream().cuda_stream
         self.H, self.W, self.M = int(H), int(W), (int(Kx), int(Ky), int(Kt))
@@ -330,7 +333,7 @@ class Batch:
     """Many independent streams advanced together (one hipGraph launch per
     step).  ``streams`` is a list of dicts with H, W, M=(Kx, Ky, Kt), gx, gy."""
 
-    def __init__(self, streams, *, tile_rows=0, kernel_variant=0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0),
+    def __init__(self, streams, *, tile_rows=0, kernel_variant=0, velocity_mode=VEL_SEARCH, fixed_v=(0.0, 0.0), temporal=TEMPORAL_OBSERVER,
                  stream=None):
         import torch
         self.specs = []
@@ -349,6 +352,7 @@ class Batch:
         p.kernel_variant = int(kernel_variant)
         p.velocity_mode = int(velocity_mode)
         p.fixed_vx, p.fixed_vy = (float(v) for v in fixed_v)
+        p.temporal = int(temporal)
         if stream is None:
             self.torch_stream = torch.cuda.Stream()
             stream = self.torch_stream.cuda_stream

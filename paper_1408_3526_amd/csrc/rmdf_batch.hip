@@ -293,6 +293,8 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
     if (st != RMDF_OK) return bail(st, std::string("stream ") + std::to_string(s) + ": " + rmdf_last_error(nullptr));
     if (p && p->velocity_mode != RMDF_VEL_SEARCH && p->velocity_mode != RMDF_VEL_FIXED)
       return bail(RMDF_E_UNSUPPORTED, "batched streams support the search and fixed velocity modes");
+    if (p && p->temporal != RMDF_TEMPORAL_OBSERVER)
+      return bail(RMDF_E_UNSUPPORTED, "batched streams use the observer state (temporal mode 0)");
     b->ctx.push_back(c);
     PixArgs a = rmdf_internal_pixargs(c);
     b->tile_rows.push_back(a.TY);

@@ -53,6 +53,7 @@ struct rmdf_ctx {
   float *gx = nullptr, *gy = nullptr, *tabB = nullptr, *tabC = nullptr;
   int variant = 0;                 // resolved kernel variant (1 generic, 2 wave-per-anchor)
   int write_features = 0;          // plain search that also writes the learned-model input
+  int temporal = 0;                // RMDF_TEMPORAL_*: observer state or ring of 2-D spectra
   // learned velocity surrogate (16x16x8): features, hidden activations, outputs, weights
   unsigned short* feat = nullptr;  // [HW][1152] BF16
   int* fidx = nullptr;             // [HW] search index (fallback)
@@ -313,6 +314,7 @@ void rmdf_params_default(rmdf_params* p) {
   p->tile_rows = 0;
   p->kernel_variant = 0;
   p->write_features = 0;
+  p->temporal = RMDF_TEMPORAL_OBSERVER;
 }
 
 rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid_x, int nvx, const float* vgrid_y,
@@ -359,6 +361,15 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   const bool w16 = rmdf::pixel16_eligible(Kx, Ky, Kt, nvx, nvy);
   if (p.kernel_variant == 2 && !w16)
     return fail(nullptr, RMDF_E_UNSUPPORTED, "kernel_variant 2 needs a 16x16x8 window and at most 21 candidates per axis");
+  if (p.temporal != RMDF_TEMPORAL_OBSERVER && p.temporal != RMDF_TEMPORAL_RING)
+    return fail(nullptr, RMDF_E_INVAL, "unknown temporal mode");
+  if (p.temporal == RMDF_TEMPORAL_RING) {
+    if (!w16 || p.kernel_variant == 1)
+      return fail(nullptr, RMDF_E_UNSUPPORTED,
+                  "the temporal ring needs the 16x16x8 window, kernel variant 2 and at most 21 candidates per axis");
+    if ((p.velocity_mode != RMDF_VEL_SEARCH && p.velocity_mode != RMDF_VEL_FIXED) || p.write_features)
+      return fail(nullptr, RMDF_E_UNSUPPORTED, "the temporal ring supports the search and fixed velocity modes");
+  }
   const bool needs16 = (p.velocity_mode == RMDF_VEL_LEARNED) || p.write_features;
   if (needs16 && (!w16 || p.kernel_variant == 1))
     return fail(nullptr, RMDF_E_UNSUPPORTED,
@@ -385,6 +396,7 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
                           : rmdf::auto_tile_rows(H, W, c->variant == 2 ? rmdf::p16_block_columns()
                                                                         : rmdf::pixel_block_columns(Kx, Ky, Kt));
   c->write_features = p.write_features ? 1 : 0;
+  c->temporal = p.temporal;
   c->nring = dt + 1;
   // NULL: the device's default (null) stream, which is also torch's default
   c->stream = static_cast<hipStream_t>(hip_stream);
@@ -463,7 +475,11 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   rmdf::PixArgs a = rmdf_internal_pixargs(c);
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
   if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
-  const int mode = (c->vmode == RMDF_VEL_LEARNED) ? 2 : (c->vmode == RMDF_VEL_REFINED) ? 3 : (c->write_features ? 1 : 0);
+  const int mode = (c->temporal == RMDF_TEMPORAL_RING) ? 4
+                   : (c->vmode == RMDF_VEL_LEARNED) ? 2
+                   : (c->vmode == RMDF_VEL_REFINED) ? 3
+                   : (c->write_features ? 1 : 0);
+  a.tcur = (int)(c->t & 0x3fffffff);
   timed_begin(c, 0, &ev);
   e = (c->variant == 2) ? rmdf::launch_pixel16(a, mode, c->stream)
                         : rmdf::launch_pixel(c->MX, c->MY, c->MZ, a, c->stream);
@@ -546,7 +562,8 @@ rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, f
   if ((e = hipMemcpyAsync(c->xy_scratch, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return hip_fail(c, e, "anchor upload");
   e = rmdf::launch_spectrum(c->MX, c->MY, c->MZ, c->st, c->W, c->xy_scratch, npix, reinterpret_cast<float2*>(spec),
-                            c->variant == 2, c->stream);
+                            c->temporal == RMDF_TEMPORAL_RING ? 2 : (c->variant == 2 ? 1 : 0),
+                            (int)((c->t - 1) & 0x3fffffff), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "spectrum launch");
   // the host array must outlive the copy
   e = hipStreamSynchronize(c->stream);

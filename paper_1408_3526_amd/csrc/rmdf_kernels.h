@@ -47,6 +47,7 @@ struct PixArgs {
   const float2* etab;          // [bx+1][2by+1]
   const int* latq;             // [nv+1] (nx << 16) | (ny & 0xffff); entry nv = fixed velocity
   int lat_q;                   // 16s
+  int tcur;                    // index of the frame being pushed (ring slot = tcur mod Mz)
 };
 
 bool shape_supported(int mx, int my, int mz);
@@ -57,13 +58,16 @@ int pixel_block_columns(int mx, int my, int mz);
 int auto_tile_rows(int H, int W, int block_columns);
 hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s);
 hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s);
-// layout16: the state is in the wave-per-anchor 16x16x8 layout
+// layout: 0 generic observer state [plane][ky][kz]; 1 wave-per-anchor 16x16x8
+// observer state; 2 ring of 2-D spectra [slot][plane][ky] whose newest frame
+// is `newest` (slot newest mod Mz)
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
-                           bool layout16, hipStream_t s);
+                           int layout, int newest, hipStream_t s);
 bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
 int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anchor kernel
 // mode: 0 search (or fixed velocity), 1 search + learned features, 2 learned
-// first pass, 3 search refined between grid points
+// first pass, 3 search refined between grid points, 4 search (or fixed
+// velocity) with the ring of 2-D spectra in place of the observer state
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 // list: [1 + H*W] ints of scratch (count, then the confident anchors)
 hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);

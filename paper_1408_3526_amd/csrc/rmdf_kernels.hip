@@ -63,35 +63,47 @@ __global__ void __launch_bounds__(256) k_pixel(PixArgs a) {
 // ---------------------------------------------------------------------------
 // Full spectrum S(k; n) = sqrt(Mz) * X at chosen anchors, unpacked to
 // [npix][Mx][My][Mz] interleaved complex.
-// IL: the wave-per-anchor 16x16x8 state layout [kz / 2][plane][ky] x (kz even,
-// kz odd); otherwise [plane][ky][kz].
-template <int MX, int MY, int MZ, bool IL>
+// LAYOUT 0: observer state [plane][ky][kz]; 1: the wave-per-anchor 16x16x8
+// observer layout [kz / 2][plane][ky] x (kz even, kz odd); 2: ring of 2-D
+// spectra [slot][plane][ky] (newest frame in slot newest mod Mz), from which
+// X_kz = (1/Mz) sum_m w^(kz m) S2(t - m) is formed here.
+template <int MX, int MY, int MZ, int LAYOUT>
 __global__ void k_spectrum(const float2* __restrict__ st, int W, const int* __restrict__ xy, int npix,
-                           float2* __restrict__ out) {
+                           float2* __restrict__ out, int newest) {
   using SH = Shape<MX, MY, MZ>;
   constexpr int N = MX * MY * MZ;
-  auto at = [](int p, int ky, int kz) {
-    return IL ? ((kz >> 1) * SH::NCOL + p * MY + ky) * 2 + (kz & 1) : (p * MY + ky) * MZ + kz;
-  };
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= npix * N) return;
   const int ip = gid / N, b = gid % N;
   int kx = b / (MY * MZ), kyy = (b / MZ) % MY, kz = b % MZ;
   const size_t pix = (size_t)xy[2 * ip + 1] * W + xy[2 * ip];
-  const float2* X = st + pix * SH::NCOL * MZ;
+  const float2* S = st + pix * SH::NCOL * MZ;
+  auto X = [&](int p, int ky, int k) -> float2 {
+    if (LAYOUT == 2) {
+      float2 acc = make_float2(0.f, 0.f);
+      for (int m = 0; m < MZ; ++m) {
+        const int slot = ((newest - m) % MZ + MZ) % MZ;
+        float sn, cs;
+        sincospif(2.0f * (float)((k * m) % MZ) / MZ, &sn, &cs);
+        acc = cadd(acc, cmul(make_float2(cs, sn), S[slot * SH::NCOL + p * MY + ky]));
+      }
+      return cscale(acc, 1.0f / MZ);
+    }
+    return S[LAYOUT == 1 ? ((k >> 1) * SH::NCOL + p * MY + ky) * 2 + (k & 1) : (p * MY + ky) * MZ + k];
+  };
   bool cj = false;
   if (2 * kx > MX) { kx = MX - kx; kyy = (MY - kyy) % MY; kz = (MZ - kz) % MZ; cj = true; }
   float2 r;
   if (kx == 0 || (SH::EVEN && 2 * kx == MX)) {
-    const float2 u = X[at(0, kyy, kz)];
+    const float2 u = X(0, kyy, kz);
     if (!SH::EVEN) r = u;
     else {
-      const float2 w = X[at(0, (MY - kyy) % MY, (MZ - kz) % MZ)];
+      const float2 w = X(0, (MY - kyy) % MY, (MZ - kz) % MZ);
       if (kx == 0) r = make_float2(0.5f * (u.x + w.x), 0.5f * (u.y - w.y));
       else         r = make_float2(0.5f * (u.y + w.y), -0.5f * (u.x - w.x));
     }
   } else {
-    r = X[at(kx, kyy, kz)];
+    r = X(kx, kyy, kz);
   }
   if (cj) r = cconj(r);
   out[gid] = cscale(r, sqrtf((float)MZ));
@@ -115,10 +127,12 @@ static hipError_t launch_row_t(const float* f, float2* rs, const float2* twx, in
   return hipGetLastError();
 }
 
-template <int MX, int MY, int MZ, bool IL = false>
-static hipError_t launch_spec_t(const float2* st, int W, const int* xy, int npix, float2* out, hipStream_t s) {
+template <int MX, int MY, int MZ, int IL>
+static hipError_t launch_spec_t(const float2* st, int W, const int* xy, int npix, float2* out, int newest,
+                                hipStream_t s) {
   const int n = npix * MX * MY * MZ;
-  hipLaunchKernelGGL((k_spectrum<MX, MY, MZ, IL>), dim3((n + 255) / 256), dim3(256), 0, s, st, W, xy, npix, out);
+  hipLaunchKernelGGL((k_spectrum<MX, MY, MZ, IL>), dim3((n + 255) / 256), dim3(256), 0, s, st, W, xy, npix, out,
+                     newest);
   return hipGetLastError();
 }
 
@@ -160,12 +174,14 @@ hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int
 }
 
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
-                           bool layout16, hipStream_t s) {
-  if (mx == 8 && my == 8 && mz == 4) return launch_spec_t<8, 8, 4>(st, W, xy, npix, out, s);
-  if (mx == 16 && my == 16 && mz == 8)
-    return layout16 ? launch_spec_t<16, 16, 8, true>(st, W, xy, npix, out, s)
-                    : launch_spec_t<16, 16, 8>(st, W, xy, npix, out, s);
-  if (mx == 9 && my == 9 && mz == 5) return launch_spec_t<9, 9, 5>(st, W, xy, npix, out, s);
+                           int layout, int newest, hipStream_t s) {
+  if (mx == 8 && my == 8 && mz == 4) return launch_spec_t<8, 8, 4, 0>(st, W, xy, npix, out, newest, s);
+  if (mx == 16 && my == 16 && mz == 8) {
+    if (layout == 2) return launch_spec_t<16, 16, 8, 2>(st, W, xy, npix, out, newest, s);
+    return layout == 1 ? launch_spec_t<16, 16, 8, 1>(st, W, xy, npix, out, newest, s)
+                       : launch_spec_t<16, 16, 8, 0>(st, W, xy, npix, out, newest, s);
+  }
+  if (mx == 9 && my == 9 && mz == 5) return launch_spec_t<9, 9, 5, 0>(st, W, xy, npix, out, newest, s);
   return hipErrorInvalidValue;
 }
 

@@ -63,6 +63,13 @@ __device__ __forceinline__ float4 ld_stream(const float4* p) {
 __device__ __forceinline__ void st_stream(float4* p, float a, float b, float c, float d) {
   __builtin_nontemporal_store(v4f{a, b, c, d}, reinterpret_cast<v4f*>(p));
 }
+__device__ __forceinline__ float2 ld2_stream(const float2* p) {
+  const v2f v = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st2_stream(float2* p, float2 v) {
+  __builtin_nontemporal_store(v2f{v.x, v.y}, reinterpret_cast<v2f*>(p));
+}
 __device__ __forceinline__ void st4(lds_v2* p, float a, float b, float c, float d) {
   *reinterpret_cast<lds_v4*>(p) = v4f{a, b, c, d};
 }
@@ -220,12 +227,44 @@ static __device__ __forceinline__ float pef_plane16(const float2* X, int kx, int
   return acc * ((kx == 0) ? (1.0f / 16.0f) : (2.0f / 16.0f));
 }
 
+// F_k = sum_n y_n j^(k n), k = 0..3.
+static __device__ __forceinline__ void dft4p(float2 y0, float2 y1, float2 y2, float2 y3, float2* F) {
+  const float2 a = f2(y0.x + y2.x, y0.y + y2.y), b = f2(y0.x - y2.x, y0.y - y2.y);
+  const float2 c = f2(y1.x + y3.x, y1.y + y3.y), d = f2(y1.x - y3.x, y1.y - y3.y);
+  F[0] = f2(a.x + c.x, a.y + c.y);
+  F[2] = f2(a.x - c.x, a.y - c.y);
+  F[1] = f2(b.x - d.y, b.y + d.x);
+  F[3] = f2(b.x + d.y, b.y - d.x);
+}
+
+// X_k = (1/8) sum_m x_m exp(+j 2 pi k m / 8): radix-2 decimation in time
+// (even and odd samples through dft4p, then the twiddles w^k, w = e^{j pi/4}).
+static __device__ __forceinline__ void dft8p_scaled(const float2* x, float2* X) {
+  float2 e[4], o[4];
+  dft4p(x[0], x[2], x[4], x[6], e);
+  dft4p(x[1], x[3], x[5], x[7], o);
+  constexpr float h = 0.70710678118654752f;
+  const float2 t[4] = {o[0], f2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y)), f2(-o[2].y, o[2].x),
+                       f2(-h * (o[3].x + o[3].y), h * (o[3].x - o[3].y))};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    X[k] = f2(0.125f * (e[k].x + t[k].x), 0.125f * (e[k].y + t[k].y));
+    X[k + 4] = f2(0.125f * (e[k].x - t[k].x), 0.125f * (e[k].y - t[k].y));
+  }
+}
+
 // MODE: 0 plain search; 1 plain search that also writes the learned model's
 // input features; 2 learned mode, first pass: features, and the complete
 // fallback result (instantaneous search, i.e. no smoothed-R state, its
 // background estimate and output), which finish16 overwrites where the
 // network is confident; 3 plain search with the peak refined between grid
-// points and the background coefficients evaluated at the refined velocity.
+// points and the background coefficients evaluated at the refined velocity;
+// 4 plain search (or fixed velocity) with the temporal part taken directly
+// instead of by the observer: a.st then holds a ring of the last Mz 2-D
+// spectra per pixel ([slot][plane][ky], slot = frame mod 8), each frame reads
+// the 7 older slots, writes the new one over the oldest, and forms
+// X_k = (1/8) sum_m w^(k m) S2(t - m) by an 8-point DFT (the observer's
+// posterior in exact arithmetic), halving the state traffic.
 template <int MODE>
 static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   lds_v2* s_all = (lds_v2*)(smem);
@@ -293,13 +332,25 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
   // [kz pair][plane][ky] x 2 complex per pixel (st16_index), one 1 KB
   // contiguous run per instruction.
   float4 SnA[MZ / 2], SnB[MZ / 2];
+  float2 RA[MZ], RB[MZ];                                 // mode 4: S2(t - m) of the row, m = 0..7
+  const int slot0 = __builtin_amdgcn_readfirstlane(a.tcur & 7);   // mode 4: slot of the new frame
   float2 nA, nB, oA = f2(0.f, 0.f), oB = f2(0.f, 0.f);   // rs(y), rs(y - My)
   {
-    const float4* src = reinterpret_cast<const float4*>(a.st + ((size_t)y0 * a.W + x) * NCOL * MZ);
+    if (MODE == 4) {
+      const float2* src = a.st + ((size_t)y0 * a.W + x) * NCOL * MZ;
 #pragma unroll
-    for (int j = 0; j < MZ / 2; ++j) {
-      SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
-      SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+      for (int m = 1; m < MZ; ++m) {
+        const int s = (slot0 - m) & 7;
+        RA[m] = ld2_stream(&src[s * NCOL + pA * MY + ky]);
+        RB[m] = ld2_stream(&src[s * NCOL + pB * MY + ky]);
+      }
+    } else {
+      const float4* src = reinterpret_cast<const float4*>(a.st + ((size_t)y0 * a.W + x) * NCOL * MZ);
+#pragma unroll
+      for (int j = 0; j < MZ / 2; ++j) {
+        SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
+        SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+      }
     }
     nA = rsA[(size_t)y0 * rstride];
     nB = rsB[(size_t)y0 * rstride];
@@ -312,12 +363,14 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
   for (int y = y0; y < y1; ++y) {
     const size_t pix = (size_t)y * a.W + x;
     float2 XA[MZ], XB[MZ];
+    if (MODE != 4) {
 #pragma unroll
-    for (int j = 0; j < MZ / 2; ++j) {
-      XA[2 * j] = f2(SnA[j].x, SnA[j].y);
-      XA[2 * j + 1] = f2(SnA[j].z, SnA[j].w);
-      XB[2 * j] = f2(SnB[j].x, SnB[j].y);
-      XB[2 * j + 1] = f2(SnB[j].z, SnB[j].w);
+      for (int j = 0; j < MZ / 2; ++j) {
+        XA[2 * j] = f2(SnA[j].x, SnA[j].y);
+        XA[2 * j + 1] = f2(SnA[j].z, SnA[j].w);
+        XB[2 * j] = f2(SnB[j].x, SnB[j].y);
+        XB[2 * j + 1] = f2(SnB[j].z, SnB[j].w);
+      }
     }
     // ---- column sliding DFT
     {
@@ -325,8 +378,18 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
       acA = f2(wy.x * acA.x - wy.y * acA.y + iA.x, wy.x * acA.y + wy.y * acA.x + iA.y);
       acB = f2(wy.x * acB.x - wy.y * acB.y + iB.x, wy.x * acB.y + wy.y * acB.x + iB.y);
     }
-    // ---- deadbeat observer (posterior rotated, innovation shared by all kz)
-    {
+    if (MODE == 4) {
+      // ---- temporal DFT over the ring: the new 2-D spectrum (1/sqrt(16)
+      // scale) replaces the oldest slot
+      RA[0] = f2(0.25f * acA.x, 0.25f * acA.y);
+      RB[0] = f2(0.25f * acB.x, 0.25f * acB.y);
+      dft8p_scaled(RA, XA);
+      dft8p_scaled(RB, XB);
+      float2* dst = a.st + pix * NCOL * MZ + slot0 * NCOL;
+      st2_stream(&dst[pA * MY + ky], RA[0]);
+      st2_stream(&dst[pB * MY + ky], RB[0]);
+    } else {
+      // ---- deadbeat observer (posterior rotated, innovation shared by all kz)
       float2 sA = f2(0.f, 0.f), sB2 = f2(0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < MZ; ++k) {
@@ -423,12 +486,22 @@ static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed,
     // issued after the loads above, which stage C waits for (vector memory
     // completes in order)
     if (y + 1 < y1) {
-      const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
+      if (MODE == 4) {
+        const float2* src = a.st + (pix + a.W) * NCOL * MZ;
 #pragma unroll
-      for (int j = 0; j < MZ / 2; ++j) {
-      SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
-      SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
-    }
+        for (int m = 1; m < MZ; ++m) {
+          const int s = (slot0 - m) & 7;
+          RA[m] = ld2_stream(&src[s * NCOL + pA * MY + ky]);
+          RB[m] = ld2_stream(&src[s * NCOL + pB * MY + ky]);
+        }
+      } else {
+        const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
+#pragma unroll
+        for (int j = 0; j < MZ / 2; ++j) {
+          SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
+          SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+        }
+      }
       nA = rsA[(size_t)(y + 1) * rstride];
       nB = rsB[(size_t)(y + 1) * rstride];
       if (y + 1 >= MY) {

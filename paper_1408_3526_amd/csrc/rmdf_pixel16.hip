@@ -70,7 +70,8 @@ hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   if (mode == 0) hipLaunchKernelGGL(p16::k_pixel16<0>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else if (mode == 1) hipLaunchKernelGGL(p16::k_pixel16_feat, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else if (mode == 2) hipLaunchKernelGGL(p16::k_pixel16<2>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(p16::k_pixel16<3>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else if (mode == 3) hipLaunchKernelGGL(p16::k_pixel16<3>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(p16::k_pixel16<4>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -179,6 +179,85 @@ def test_parity_16x16x8_tiny_frames(orc, H, W, tile, variant):
     check_velocity_and_output(gres, r, fr, len(g), g, g)
 
 
+# Temporal ring (the temporal DFT taken directly over a ring of the last Mz
+# 2-D spectra instead of the observer): the same spectrum, so the same bars.
+def test_parity_16x16x8_temporal_ring(orc):
+    b = _binding()
+    sc = scenes.flow_scene(5, H=40, W=47, T=20, n_targets=3, band_width=(8, 12))
+    g = scenes.grid(-4, 4, 0.5)
+    M = (16, 16, 8)
+    xs, ys = np.array([0, 46, 20, 15, 46]), np.array([0, 39, 20, 33, 0])
+    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), tile_rows=16, temporal=b.TEMPORAL_RING)
+    r = orc.run(_cfg(orc, 40, 47, M, g, g), sc.frames, want_rs=True, want_spec=True)
+    check_spec(gres, r, xs, ys)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
+
+
+@pytest.mark.parametrize("H,W,tile", [(3, 5, 32), (17, 1, 4), (1, 9, 8)])
+def test_parity_temporal_ring_tiny_frames(orc, H, W, tile):
+    b = _binding()
+    rng = np.random.default_rng(H * 100 + W + 7)
+    fr = (rng.normal(size=(19, H, W)) * 5 + 20).astype(np.float32)
+    g = scenes.grid(-2, 2, 1.0)
+    M = (16, 16, 8)
+    gres = run_gpu(fr, M, g, g, tile_rows=tile, temporal=b.TEMPORAL_RING)
+    r = orc.run(_cfg(orc, H, W, M, g, g), fr, want_rs=True)
+    check_rs(gres, r)
+    check_velocity_and_output(gres, r, fr, len(g), g, g)
+
+
+def test_temporal_ring_matches_observer_and_pef_null(orc):
+    """The ring and the observer give the same output within FP32 rounding;
+    in fixed-velocity mode the ring's filter nulls translating band-limited
+    clutter like the observer's."""
+    b = _binding()
+    sc = scenes.flow_scene(8, H=64, W=80, T=24, n_targets=4)
+    g = scenes.grid(-4, 4, 0.5)
+    a = run_gpu(sc.frames, (16, 16, 8), g, g)
+    r = run_gpu(sc.frames, (16, 16, 8), g, g, temporal=b.TEMPORAL_RING)
+    rms = float(np.sqrt(np.mean(sc.frames.astype(np.float64) ** 2)))
+    # (ties of the argmax, e.g. in the first frames where R vanishes, may
+    # resolve differently under different rounding; parity with the oracle,
+    # tie rule included, is checked above)
+    same = a["idx"] == r["idx"]
+    assert same[4:].mean() >= 0.99
+    assert np.abs(a["out"] - r["out"])[same].max() <= 1e-4 * rms
+    rng = np.random.default_rng(6)
+    M, B, v = (16, 16, 8), 5, (1.5, -0.75)
+    H, W, T = M[1] + 9, M[0] + 11, 2 * M[2] + 4
+    ys, xs = np.mgrid[0:H, 0:W].astype(float)
+    fr = np.full((T, H, W), 10.0)
+    comps = [(rng.integers(-B, B + 1), rng.integers(-B, B + 1), rng.uniform(0.5, 2.0),
+              rng.uniform(0, 2 * np.pi)) for _ in range(12)]
+    for t in range(T):
+        for kx, ky, amp, ph in comps:
+            fr[t] += amp * np.cos(2 * np.pi * (kx * (xs - v[0] * t) / M[0] + ky * (ys - v[1] * t) / M[1]) + ph)
+    fr = fr.astype(np.float32)
+    gres = run_gpu(fr, M, np.zeros(1), np.zeros(1), Bx=B, By=B, velocity_mode=b.VEL_FIXED, fixed_v=v,
+                   temporal=b.TEMPORAL_RING)
+    ref = orc.run(_cfg(orc, H, W, M, np.zeros(1), np.zeros(1), Bx=B, By=B, vmode=2, fvx=v[0], fvy=v[1]), fr)
+    frms = float(np.sqrt(np.mean(fr.astype(np.float64) ** 2)))
+    assert np.abs(gres["out"] - ref["out"]).max() <= 1e-3 * frms
+
+
+def test_temporal_ring_arguments():
+    b = _binding()
+    g = scenes.grid(-2, 2, 1.0)
+    for kw in [dict(M=(8, 8, 4)), dict(M=(16, 16, 8), kernel_variant=1),
+               dict(M=(16, 16, 8), velocity_mode=b.VEL_REFINED), dict(M=(16, 16, 8), write_features=True)]:
+        M = kw.pop("M")
+        with pytest.raises(b.RmdfError) as e:
+            b.Filter(20, 20, *M, g, g, temporal=b.TEMPORAL_RING, **kw)
+        assert e.value.status == b.RMDF_E_UNSUPPORTED, kw
+    with pytest.raises(b.RmdfError) as e:
+        b.Filter(20, 20, 16, 16, 8, g, g, temporal=2)
+    assert e.value.status == b.RMDF_E_INVAL
+    with pytest.raises(b.RmdfError) as e:
+        b.Batch([dict(H=20, W=20, M=(16, 16, 8), gx=g, gy=g)], temporal=b.TEMPORAL_RING)
+    assert e.value.status == b.RMDF_E_UNSUPPORTED
+
+
 def test_parity_paper_configuration(orc):
     """The paper's parameters: 9x9x5 window (K = 4, 4, 2), B = 3, m' = K,
     17x17 grid at 0.25 px/frame, on the paper's simulated scene."""
@@ -370,6 +449,17 @@ def test_sampled_parity_640x512_window_16x16x8(orc):
     g = scenes.grid(-4, 4, 0.5)
     pts = _sample_points(np.random.default_rng(0), 512, 640, 20)
     _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T)
+
+
+def test_sampled_parity_640x512_temporal_ring(orc):
+    """The temporal ring at the benchmark workload's shape, sampled anchors
+    (more frames than the ring holds, so every slot is reused)."""
+    b = _binding()
+    T = 20
+    sc = scenes.flow_scene(1, H=512, W=640, T=T, n_targets=20)
+    g = scenes.grid(-4, 4, 0.5)
+    pts = _sample_points(np.random.default_rng(3), 512, 640, 12)
+    _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T, temporal=b.TEMPORAL_RING)
 
 
 def test_sampled_parity_1280x1024_window_16x16x8(orc):
