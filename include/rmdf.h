@@ -278,6 +278,14 @@ rmdf_status rmdf_batch_output(rmdf_batch *b, int s, float *out_dev, float *vxy_d
 rmdf_status rmdf_batch_stream_ctx(rmdf_batch *b, int s, rmdf_ctx **ctx);
 /* Rows per work tile for stream s (s = -1: all); rebuilds the graph. */
 rmdf_status rmdf_batch_set_tiles(rmdf_batch *b, int s, int tile_rows);
+/* Schedule of the per-pixel tiles within a step; rebuilds the graph.
+ * 0 (default): one persistent kernel per tile family, largest family first;
+ * 1: one persistent kernel for the 16x16x8 wave-per-anchor, 8x8x4 and 9x9x5
+ *    families, their work items interleaved in proportion;
+ * 2: as 0, with the 8x8x4 and 9x9x5 kernels on a parallel branch of the
+ *    graph (they may run beside the 16x16x8 kernel).
+ * The results do not depend on the schedule.  The autotuner tries all three. */
+rmdf_status rmdf_batch_set_schedule(rmdf_batch *b, int schedule);
 /* Pick rows per tile for each size class and the persistent grid size by
  * timing whole steps (iters timed launches per candidate).  The streams
  * advance while tuning (whatever the input slots hold is consumed).  A text

@@ -81,6 +81,7 @@ _SIGS = {
     "rmdf_batch_output": (_I, [_VP, _I, _VP, _VP, _VP]),
     "rmdf_batch_stream_ctx": (_I, [_VP, _I, ctypes.POINTER(_VP)]),
     "rmdf_batch_set_tiles": (_I, [_VP, _I, _I]),
+    "rmdf_batch_set_schedule": (_I, [_VP, _I]),
     "rmdf_batch_autotune": (_I, [_VP, _I, ctypes.c_char_p, _SZ]),
     "rmdf_batch_set_timing": (_I, [_VP, _I]),
     "rmdf_batch_latency": (_I, [_VP, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float),
@@ -405,6 +406,11 @@ class Batch:
 
     def set_tiles(self, s: int, tile_rows: int):
         _bcheck(lib().rmdf_batch_set_tiles(self.b, int(s), int(tile_rows)), self.b)
+
+    def set_schedule(self, schedule: int):
+        """0 one kernel per tile family, 1 one mixed kernel, 2 small families
+        on a parallel graph branch (rmdf_batch_set_schedule)."""
+        _bcheck(lib().rmdf_batch_set_schedule(self.b, int(schedule)), self.b)
 
     def autotune(self, iters: int = 5) -> str:
         buf = ctypes.create_string_buffer(4096)

@@ -112,6 +112,38 @@ k_batch_tiles(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items
   });
 }
 
+// One persistent kernel for the wave-per-anchor 16x16x8 tiles and the 8x8x4
+// and 9x9x5 tiles: a single queue (queue[0]) whose items interleave the
+// families in proportion, so the small, latency-bound tiles run beside the
+// memory-bound 16x16x8 ones instead of after them.  Register budget of the
+// largest tile (two workgroups per CU), LDS of the largest family.  The
+// generic 16x16x8 tile keeps its own kernel (its register demand would push
+// this one into scratch).
+constexpr size_t MIXED_SMEM = cmax(cmax(KindSmem<KIND_884>::v, KindSmem<KIND_995>::v), KindSmem<KIND_16W>::v);
+constexpr bool in_mixed(int kind) { return kind != KIND_16G; }
+
+// The small tiles are called rather than inlined into the mixed kernel: each
+// keeps its own register allocation, and the 16x16x8 path (inlined) keeps its
+// registers free of spills.
+static __device__ __attribute__((noinline)) void tile884(const PixArgs& a, const float* rd, int xb, int yb, char* smem) {
+  pixel_tile<8, 8, 4>(a, rd, xb, yb, smem);
+}
+static __device__ __attribute__((noinline)) void tile995(const PixArgs& a, const float* rd, int xb, int yb, char* smem) {
+  pixel_tile<9, 9, 5>(a, rd, xb, yb, smem);
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_batch_mixed(const BatchPixDesc* __restrict__ d, const int4* __restrict__ items, int n_items, BatchState bs) {
+  __shared__ __align__(16) char smem[MIXED_SMEM];
+  __shared__ unsigned int s_item;
+  item_loop(d, items, n_items, bs.queue, bs.t, &s_item, [&](const BatchPixDesc& bd, const float* rd, int4 w) {
+    const int kind = __builtin_amdgcn_readfirstlane(bd.kind);
+    if (kind == KIND_16W) p16::pixel16_tile<0>(bd.a, rd, w.y, w.z, smem);
+    else if (kind == KIND_884) tile884(bd.a, rd, w.y, w.z, smem);
+    else tile995(bd.a, rd, w.y, w.z, smem);
+  });
+}
+
 // End of a step: every stream has consumed one frame; re-arm the queues (a
 // kernel, not a memset, so the same code is safe to capture).
 __global__ void k_batch_advance(BatchState bs, int n_streams) {
@@ -135,6 +167,13 @@ struct rmdf_batch {
   bool own_stream = false;
   std::vector<int> tile_rows;        // per stream
   int grid_mult = 1;                 // persistent workgroups per resident slot
+  // schedule of the pixel tiles: 0 one kernel per family, one after another;
+  // 1 one kernel for all families (k_batch_mixed); 2 one kernel per family,
+  // the small families on a second graph branch beside the 16x16x8 kernels
+  int schedule = 0;
+  int mixed_blocks = 0;
+  hipStream_t side = nullptr;        // second capture stream (schedule 2)
+  hipEvent_t fork = nullptr, join = nullptr;
   // device
   RowDesc* d_row = nullptr;
   BatchPixDesc* d_pix = nullptr;
@@ -215,6 +254,35 @@ static hipError_t rebuild(rmdf_batch* b) {
     iv[i] = items[i].w;
     b->n_items[pd[items[i].w.x].kind] += 1;
   }
+  int n_mixed = 0;
+  const bool mixed = (b->schedule == 1);
+  if (mixed) {
+    // the generic 16x16x8 items keep their family's place; the others are
+    // interleaved: item j of a family with n items sits at (j + 1/2) / n of
+    // the mixed queue, so every family advances at the same relative rate and
+    // the queue still ends with each family's smallest items
+    std::vector<std::pair<double, int4>> keyed;
+    int first = 0;
+    for (int k = 0; k < NKIND; ++k) {
+      if (in_mixed(k))
+        for (int j = 0; j < b->n_items[k]; ++j) keyed.push_back({(j + 0.5) / b->n_items[k], iv[first + j]});
+      first += b->n_items[k];
+    }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const std::pair<double, int4>& p, const std::pair<double, int4>& q) { return p.first < q.first; });
+    // layout: [generic 16x16x8 items][mixed items]
+    std::vector<int4> jv;
+    jv.reserve(iv.size());
+    first = 0;
+    for (int k = 0; k < NKIND; ++k) {
+      if (!in_mixed(k))
+        for (int j = 0; j < b->n_items[k]; ++j) jv.push_back(iv[first + j]);
+      first += b->n_items[k];
+    }
+    for (auto& kv : keyed) jv.push_back(kv.second);
+    iv.swap(jv);
+    n_mixed = (int)keyed.size();
+  }
   if (b->d_items) hipFree(b->d_items);
   b->d_items = nullptr;
   if ((e = hipMalloc(&b->d_items, sizeof(int4) * std::max<size_t>(iv.size(), 1))) != hipSuccess) return e;
@@ -233,24 +301,45 @@ static hipError_t rebuild(rmdf_batch* b) {
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern[k], 256, 0);
     b->blocks[k] = std::min(b->n_items[k], cus * std::max(occ, 1) * b->grid_mult);
   }
+  {
+    int occ = 0;
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void*>(k_batch_mixed), 256, 0);
+    b->mixed_blocks = std::min(n_mixed, cus * std::max(occ, 1) * b->grid_mult);
+  }
 
   BatchState bs{b->d_t, b->d_queue};
   if ((e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_row_batch, dim3(b->row_blocks), dim3(256), 0, b->stream, b->d_row, b->n,
                      (const long long*)b->d_t);
-  // the largest tiles first
+  if (mixed && b->mixed_blocks > 0)
+    hipLaunchKernelGGL(k_batch_mixed, dim3(b->mixed_blocks), dim3(256), 0, b->stream, b->d_pix,
+                       (const int4*)b->d_items + (iv.size() - n_mixed), n_mixed, bs);
+  // schedule 2: fork after the row pass, the small families on the side branch
+  const bool branch = (b->schedule == 2) && (b->blocks[KIND_884] > 0 || b->blocks[KIND_995] > 0);
+  if (branch) {
+    hipEventRecord(b->fork, b->stream);
+    hipStreamWaitEvent(b->side, b->fork, 0);
+  }
+  // per family: the largest tiles first (in mixed mode only the generic
+  // 16x16x8 family, whose items open the list, on queue[KIND_16G])
   const int order[NKIND] = {KIND_16W, KIND_16G, KIND_995, KIND_884};
   for (int k : order) {
-    if (b->blocks[k] == 0) continue;
+    if ((mixed && in_mixed(k)) || b->blocks[k] == 0) continue;
     int first = 0;
-    for (int j = 0; j < k; ++j) first += b->n_items[j];
+    if (!mixed)
+      for (int j = 0; j < k; ++j) first += b->n_items[j];
     const int4* it = (const int4*)b->d_items + first;
+    const hipStream_t st = (branch && (k == KIND_884 || k == KIND_995)) ? b->side : b->stream;
     switch (k) {
-      case KIND_884: hipLaunchKernelGGL(k_batch_tiles<KIND_884>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
-      case KIND_995: hipLaunchKernelGGL(k_batch_tiles<KIND_995>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
-      case KIND_16G: hipLaunchKernelGGL(k_batch_tiles<KIND_16G>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
-      default: hipLaunchKernelGGL(k_batch_tiles<KIND_16W>, dim3(b->blocks[k]), dim3(256), 0, b->stream, b->d_pix, it, b->n_items[k], bs); break;
+      case KIND_884: hipLaunchKernelGGL(k_batch_tiles<KIND_884>, dim3(b->blocks[k]), dim3(256), 0, st, b->d_pix, it, b->n_items[k], bs); break;
+      case KIND_995: hipLaunchKernelGGL(k_batch_tiles<KIND_995>, dim3(b->blocks[k]), dim3(256), 0, st, b->d_pix, it, b->n_items[k], bs); break;
+      case KIND_16G: hipLaunchKernelGGL(k_batch_tiles<KIND_16G>, dim3(b->blocks[k]), dim3(256), 0, st, b->d_pix, it, b->n_items[k], bs); break;
+      default: hipLaunchKernelGGL(k_batch_tiles<KIND_16W>, dim3(b->blocks[k]), dim3(256), 0, st, b->d_pix, it, b->n_items[k], bs); break;
     }
+  }
+  if (branch) {
+    hipEventRecord(b->join, b->side);
+    hipStreamWaitEvent(b->stream, b->join, 0);
   }
   hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(256), 0, b->stream, bs, b->n);
   if ((e = hipStreamEndCapture(b->stream, &b->graph)) != hipSuccess) return e;
@@ -280,6 +369,9 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
   }
   auto bail = [&](rmdf_status st, const std::string& m) {
     for (auto* c : b->ctx) rmdf_destroy(c);
+    if (b->side) hipStreamDestroy(b->side);
+    if (b->fork) hipEventDestroy(b->fork);
+    if (b->join) hipEventDestroy(b->join);
     if (b->own_stream) hipStreamDestroy(b->stream);
     delete b;
     return bfail(nullptr, st, m);
@@ -316,6 +408,11 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
     base += r.chunks * a.H;
   }
   b->row_blocks = base;
+  // second branch of the captured step (schedule 2); default priority
+  if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)
+    return bail(RMDF_E_DEVICE, "stream or event creation failed");
   b->t.assign(n, 0);
   if ((e = hipMalloc(&b->d_row, sizeof(RowDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
   if ((e = hipMalloc(&b->d_pix, sizeof(BatchPixDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
@@ -393,6 +490,15 @@ rmdf_status rmdf_batch_set_tiles(rmdf_batch* b, int s, int tile_rows) {
   hipStreamSynchronize(b->stream);
   for (int i = 0; i < b->n; ++i)
     if (s < 0 || i == s) b->tile_rows[i] = tile_rows;
+  hipError_t e = rebuild(b);
+  if (e != hipSuccess) return bfail(b, RMDF_E_DEVICE, hipGetErrorString(e));
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_batch_set_schedule(rmdf_batch* b, int schedule) {
+  if (!b || schedule < 0 || schedule > 2) return bfail(b, RMDF_E_INVAL, "schedule must be 0, 1 or 2");
+  hipStreamSynchronize(b->stream);
+  b->schedule = schedule;
   hipError_t e = rebuild(b);
   if (e != hipSuccess) return bfail(b, RMDF_E_DEVICE, hipGetErrorString(e));
   return RMDF_OK;
@@ -490,9 +596,22 @@ rmdf_status rmdf_batch_autotune(rmdf_batch* b, int iters, char* report, size_t r
     if (t < best_all) { best_all = t; best_mult = m; }
   }
   b->grid_mult = best_mult;
+  // schedule of the tile families
+  int best_sched = b->schedule;
+  for (int sc = 0; sc < 3; ++sc) {
+    if (sc == best_sched) continue;
+    b->schedule = sc;
+    if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
+    const float t = measure();
+    if (t < best_all) { best_all = t; best_sched = sc; }
+  }
+  b->schedule = best_sched;
   if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
-  char line[160];
-  std::snprintf(line, sizeof line, "persistent workgroups per slot %d; median step %.3f ms\n", best_mult, best_all);
+  static const char* sched_name[3] = {"one kernel per tile family", "one kernel for all tile families",
+                                      "one kernel per tile family, small families on a parallel branch"};
+  char line[200];
+  std::snprintf(line, sizeof line, "persistent workgroups per slot %d; %s; median step %.3f ms\n", best_mult,
+                sched_name[b->schedule], best_all);
   rep += line;
   b->timing = was;
   if (report && report_len) {
@@ -507,6 +626,9 @@ rmdf_status rmdf_batch_destroy(rmdf_batch* b) {
   hipStreamSynchronize(b->stream);
   for (auto& pr : b->ev) { hipEventDestroy(pr.first); hipEventDestroy(pr.second); }
   free_graph(b);
+  if (b->side) hipStreamDestroy(b->side);
+  if (b->fork) hipEventDestroy(b->fork);
+  if (b->join) hipEventDestroy(b->join);
   hipFree(b->d_items);
   hipFree(b->d_row);
   hipFree(b->d_pix);

@@ -155,7 +155,7 @@ static __device__ __forceinline__ float2 coeff_at(int kx, int ky, int kz, float 
 // One work tile: PPB adjacent anchor columns starting at xb*PPB, rows
 // [yb*TY, yb*TY + TY).  All 256 threads of the block must call it.
 template <int MX, int MY, int MZ>
-static __device__ void pixel_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
+static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   using SH = Shape<MX, MY, MZ>;
   constexpr int NP = SH::NP, NXH = SH::NXH, NCOL = SH::NCOL, NCOLP = SH::NCOLP, PPB = SH::PPB;
   constexpr bool EVEN = SH::EVEN;

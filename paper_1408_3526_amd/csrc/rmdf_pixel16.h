@@ -266,7 +266,7 @@ static __device__ __forceinline__ void dft8p_scaled(const float2* x, float2* X) 
 // X_k = (1/8) sum_m w^(k m) S2(t - m) by an 8-point DFT (the observer's
 // posterior in exact arithmetic), halving the state traffic.
 template <int MODE>
-static __device__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
+static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   lds_v2* s_all = (lds_v2*)(smem);
   lds_v4* s_tab = (lds_v4*)(smem + sizeof(float2) * WAVES * SB_ELEMS);  // tabB rows, then tabC rows
   lds_v2* s_g = (lds_v2*)(smem + sizeof(float2) * WAVES * SB_ELEMS + sizeof(float4) * 2 * NV1_MAX * 4);

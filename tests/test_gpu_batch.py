@@ -22,12 +22,16 @@ def _streams():
     ]
 
 
-@pytest.mark.parametrize("tile", [8, 32])
-def test_batch_graph_replays_equal_eager(tile):
+@pytest.mark.parametrize("tile,schedule", [(8, 0), (32, 0), (8, 1), (32, 2)])
+def test_batch_graph_replays_equal_eager(tile, schedule):
+    """Every schedule of the tile families (one kernel per family, one mixed
+    kernel, small families on a parallel graph branch) gives the eager
+    single-stream results bit for bit."""
     from paper_1408_3526_amd import binding
     st = _streams()
     T = 10
     b = binding.Batch(st, tile_rows=tile)
+    b.set_schedule(schedule)
     singles = [binding.Filter(s["H"], s["W"], *s["M"], s["gx"], s["gy"], tile_rows=tile) for s in st]
     dev = [torch.from_numpy(s["frames"]).cuda() for s in st]
     for t in range(T):
