@@ -107,12 +107,18 @@ void rmdf_params_default(rmdf_params *p);
  * frame; candidate index i = iy * nvx + ix).  p == NULL: defaults.
  * hip_stream: the hipStream_t every call of this context enqueues on; NULL
  * means the device's default (null) stream.
- * Allocates all device state (observer state H*W*Kx*Ky*Kt/2 complex FP32,
+ * Allocates all device state (observer state H*W*Kx*Ky*Kt/2 complex FP32, or
+ * the ring of Kt 2-D spectra of the same size with RMDF_TEMPORAL_RING,
  * smoothed autocorrelation H*W*nvx*nvy FP32, row spectra, a (m'_t+1)-frame
  * delay ring, tables) and zeroes it.
  * Compiled window shapes: 8x8x4, 16x16x8, 9x9x5 (others: RMDF_E_UNSUPPORTED).
  * Errors: RMDF_E_INVAL (H, W < 1 or H > 65535; bad B, m', alpha; nvx, nvy outside [1, 33],
- * non-finite grid; out == NULL), RMDF_E_DEVICE, RMDF_E_NOMEM. */
+ * non-finite grid; unknown velocity or temporal mode; RMDF_VEL_REFINED with a
+ * grid that is not strictly increasing; out == NULL), RMDF_E_UNSUPPORTED (a
+ * mode the chosen kernel lacks: the learned model, write_features and the
+ * temporal ring need the 16x16x8 wave-per-anchor kernel; the ring and
+ * write_features exclude the learned and refined modes), RMDF_E_DEVICE,
+ * RMDF_E_NOMEM. */
 rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt,
                         const float *vgrid_x, int nvx, const float *vgrid_y, int nvy,
                         const rmdf_params *p, void *hip_stream, rmdf_ctx **out);
