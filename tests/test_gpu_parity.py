@@ -385,6 +385,21 @@ def test_state_errors():
     f.close()
 
 
+def test_auto_tile_rows():
+    """Default tile height: 32 rows where the frame has >= 2048 work tiles,
+    halved (down to 1) on smaller frames; an explicit value is kept."""
+    b = _binding()
+    g = scenes.grid(-4, 4, 0.5)
+    for (H, W, M, want) in [(512, 640, (16, 16, 8), 32), (1024, 1280, (16, 16, 8), 32), (64, 64, (9, 9, 5), 1),
+                            (64, 64, (8, 8, 4), 1), (256, 320, (8, 8, 4), 4), (128, 160, (16, 16, 8), 2)]:
+        f = b.Filter(H, W, *M, g, g)
+        assert f.tile_rows() == want, (H, W, M, f.tile_rows())
+        f.close()
+    f = b.Filter(64, 64, 8, 8, 4, g, g, tile_rows=24)
+    assert f.tile_rows() == 24
+    f.close()
+
+
 def test_kernel_variant_limits():
     """The one-wavefront-per-anchor kernel takes at most 21 candidates per
     axis; beyond that the automatic choice is the generic kernel and an

@@ -142,6 +142,41 @@ def test_refined_ragged_8x8x4(orc, H, W, tile):
     check_refined(gres, r["rs_all"], r["en_all"], r["idx"], r["vxy"], r["out"], fr, g)
 
 
+@pytest.mark.parametrize("variant", [2, 1])
+def test_refined_nonuniform_grid(orc, variant):
+    """A strictly increasing but non-uniform grid: the vertex through three
+    unequally spaced points (both kernels)."""
+    T, H, W = 9, 20, 23
+    sc = scenes.flow_scene(11, H=H, W=W, T=T, n_targets=1, band_width=(4, 6))
+    g = np.array([-3.5, -2.0, -1.2, -0.5, 0.0, 0.3, 0.9, 1.6, 2.5, 3.6])
+    M = (16, 16, 8)
+    gres = run_gpu(sc.frames, M, g, kernel_variant=variant)
+    r = _oracle_run(orc, "nonuniform", _cfg(orc, H, W, M, g), sc.frames)
+    nvx = len(g)
+    n_well = 0
+    for t in range(T):
+        rs = r["rs_all"][t]
+        srt = np.sort(rs, axis=-1)
+        scale = np.maximum(np.maximum(np.abs(rs).max(axis=-1), 1e-3 * r["en_all"][t]), 1e-30)
+        tied = (srt[..., -1] - srt[..., -2]) <= 1e-4 * scale
+        agree = gres["idx"][t] == r["idx"][t]
+        if (~tied).any():
+            assert agree[~tied].mean() >= 0.999
+        oi = r["idx"][t]
+        ix, iy = oi % nvx, oi // nvx
+        r1 = _take(rs, oi)
+        well = agree & ~tied
+        for inner, step in (((ix > 0) & (ix < nvx - 1), 1), ((iy > 0) & (iy < nvx - 1), nvx)):
+            lo = _take(rs, np.clip(oi - step, 0, rs.shape[-1] - 1)) - r1
+            hi = _take(rs, np.clip(oi + step, 0, rs.shape[-1] - 1)) - r1
+            well &= ~inner | (-(lo + hi) / scale >= 1e-2)
+        dv = np.abs(gres["vxy"][t].astype(np.float64) - r["vxy"][t]).max(axis=-1)
+        if well.any():
+            assert dv[well].max() <= 2e-3 * 0.3, (t, dv[well].max())
+        n_well += int(well.sum())
+    assert n_well > 0.4 * T * H * W, n_well
+
+
 def test_refined_sampled_640x512(orc):
     """The benchmark workload's shape and launch configuration in mode 3;
     the oracle computes sampled anchors from their direct window spectra."""
