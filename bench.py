@@ -254,7 +254,7 @@ def refined_leg(dev, sc, M, g, steps, warmup):
     for i in range(warmup):
         f.push_frame(dev[i % T])
     torch.cuda.synchronize()
-    f.set_timing(True)
+    f.set_timing(kernels=[0])
     f.kernel_time(0)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -298,7 +298,7 @@ def ring_leg(dev, M, g, steps, warmup):
     for i in range(warmup):
         f.push_frame(dev[i % T])
     torch.cuda.synchronize()
-    f.set_timing(True)
+    f.set_timing(kernels=[0])
     f.kernel_time(0)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -459,10 +459,10 @@ def main():
     for i in range(args.warmup):
         f.push_frame(dev[i % T])
     torch.cuda.synchronize()
-    f.set_timing(True)
+    # timed region: only the dominant (pixel) kernel carries HIP events, for
+    # the roofline; every timed launch adds two event records to the stream
+    f.set_timing(kernels=[0])
     f.kernel_time(0)   # reset counters
-    f.kernel_time(1)
-    f.kernel_time(2)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
@@ -473,7 +473,15 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     ms = e0.elapsed_time(e1)
-    kms = {k: f.kernel_time(k) for k in (0, 1, 2)}
+    kms = {0: f.kernel_time(0)}
+    # the other kernels' times from a short untimed pass with every kernel timed
+    f.set_timing(True)
+    for k in (1, 2):
+        f.kernel_time(k)
+    for i in range(min(args.steps, 100)):
+        f.push_frame(dev[(args.warmup + args.steps + i) % T])
+    for k in (1, 2):
+        kms[k] = f.kernel_time(k)
     f.set_timing(False)
     out = f.output()
     assert torch.isfinite(out).all()

@@ -159,9 +159,11 @@ rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);
 /* Per-kernel timing with HIP events on the context stream (off by default).
  * which: 0 = pixel kernel, 1 = row sliding-DFT kernel, 2 = ingest,
  * 3 = learned-model network (three kernels), 4 = learned-mode finish kernel.
- * Returns the summed milliseconds and the number of timed launches since the
- * last reset (reading synchronises the stream). */
-rmdf_status rmdf_set_timing(rmdf_ctx *ctx, int on);
+ * rmdf_set_timing: mask bit w times kernel w; 0 = off, -1 = all (each timed
+ * launch adds two event records to the stream, so time only what is needed).
+ * rmdf_kernel_time returns the summed milliseconds and the number of timed
+ * launches since the last reset (reading synchronises the stream). */
+rmdf_status rmdf_set_timing(rmdf_ctx *ctx, int mask);
 rmdf_status rmdf_kernel_time(rmdf_ctx *ctx, int which, double *ms, long long *launches);
 
 /* ---- Learned velocity surrogate (16x16x8 window) ----------------------

@@ -249,8 +249,11 @@ class Filter:
         _check(lib().rmdf_smoothed_r(self.ctx, out.data_ptr()), self.ctx)
         return out
 
-    def set_timing(self, on: bool):
-        _check(lib().rmdf_set_timing(self.ctx, int(bool(on))), self.ctx)
+    def set_timing(self, on: bool = True, kernels=None):
+        """Per-kernel HIP-event timing: all kernels (on), none, or only those
+        listed in kernels (0 pixel, 1 row, 2 ingest, 3 network, 4 finish)."""
+        mask = (-1 if on else 0) if kernels is None else sum(1 << int(k) for k in kernels)
+        _check(lib().rmdf_set_timing(self.ctx, int(mask)), self.ctx)
 
     def kernel_time(self, which: int):
         ms, n = ctypes.c_double(), ctypes.c_longlong()

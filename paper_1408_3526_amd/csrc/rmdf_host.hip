@@ -69,7 +69,8 @@ struct rmdf_ctx {
   size_t bytes = 0;
   std::vector<void*> allocs;
   // timing
-  bool timing = false;
+  int timing = 0;                  // bit w: time kernel w (rmdf_kernel_time numbering)
+  std::vector<hipEvent_t> event_pool;   // recycled timing events
   std::vector<EventPair> events;
   double ms[5] = {0, 0, 0, 0, 0};
   long long launches[5] = {0, 0, 0, 0, 0};
@@ -102,6 +103,8 @@ static void free_all(rmdf_ctx* c) {
   c->allocs.clear();
   for (auto& ev : c->events) { hipEventDestroy(ev.a); hipEventDestroy(ev.b); }
   c->events.clear();
+  for (hipEvent_t e : c->event_pool) hipEventDestroy(e);
+  c->event_pool.clear();
   if (c->own_stream && c->stream) hipStreamDestroy(c->stream);
   c->stream = nullptr;
 }
@@ -443,15 +446,26 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   return RMDF_OK;
 }
 
+static hipEvent_t pooled_event(rmdf_ctx* c) {
+  hipEvent_t e = nullptr;
+  if (!c->event_pool.empty()) {
+    e = c->event_pool.back();
+    c->event_pool.pop_back();
+  } else {
+    hipEventCreate(&e);
+  }
+  return e;
+}
 static void timed_begin(rmdf_ctx* c, int which, EventPair* ev) {
-  if (!c->timing) return;
-  hipEventCreate(&ev->a);
-  hipEventCreate(&ev->b);
+  ev->which = -1;
+  if (!((c->timing >> which) & 1)) return;
+  ev->a = pooled_event(c);
+  ev->b = pooled_event(c);
   ev->which = which;
   hipEventRecord(ev->a, c->stream);
 }
 static void timed_end(rmdf_ctx* c, EventPair* ev) {
-  if (!c->timing) return;
+  if (ev->which < 0) return;
   hipEventRecord(ev->b, c->stream);
   c->events.push_back(*ev);
 }
@@ -582,7 +596,7 @@ rmdf_status rmdf_smoothed_r(rmdf_ctx* c, float* rs) {
 
 rmdf_status rmdf_set_timing(rmdf_ctx* c, int on) {
   if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
-  c->timing = on != 0;
+  c->timing = on < 0 ? 0x1f : (on & 0x1f);
   return RMDF_OK;
 }
 
@@ -595,8 +609,8 @@ rmdf_status rmdf_kernel_time(rmdf_ctx* c, int which, double* ms, long long* laun
     hipEventElapsedTime(&t, ev.a, ev.b);
     c->ms[ev.which] += t;
     c->launches[ev.which] += 1;
-    hipEventDestroy(ev.a);
-    hipEventDestroy(ev.b);
+    c->event_pool.push_back(ev.a);
+    c->event_pool.push_back(ev.b);
   }
   c->events.clear();
   *ms = c->ms[which];
