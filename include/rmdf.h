@@ -124,8 +124,8 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt,
                         const rmdf_params *p, void *hip_stream, rmdf_ctx **out);
 
 /* Push the next frame (device pointer, H*W FP32) and run the whole per-frame
- * path on the context stream: frame ingest into the delay ring, row sliding
- * DFT, then the per-pixel kernel (column sliding DFT, observer update,
+ * path on the context stream: the row sliding DFT (which also stores the frame
+ * into the delay ring), then the per-pixel kernel (column sliding DFT, observer update,
  * high-pass + Hann + power spectrum, autocorrelation on the grid, smoothing,
  * argmax, velocity-tuned background estimate, output).
  * Errors: RMDF_E_INVAL (NULL), RMDF_E_DEVICE (launch failure). */
@@ -157,7 +157,8 @@ rmdf_status rmdf_spectrum(rmdf_ctx *ctx, int npix, const int *xs, const int *ys,
 rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);
 
 /* Per-kernel timing with HIP events on the context stream (off by default).
- * which: 0 = pixel kernel, 1 = row sliding-DFT kernel, 2 = ingest,
+ * which: 0 = pixel kernel, 1 = row sliding-DFT kernel (which also copies the
+ * frame into the delay ring), 2 = unused (no separate ingest kernel),
  * 3 = learned-model network (three kernels), 4 = learned-mode finish kernel.
  * rmdf_set_timing: mask bit w times kernel w; 0 = off, -1 = all (each timed
  * launch adds two event records to the stream, so time only what is needed).

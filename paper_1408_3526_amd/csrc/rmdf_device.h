@@ -35,10 +35,12 @@ struct RowShape {
 
 // One (row y, chunk of RCX columns starting at x0).  Non-finite samples are
 // read as 0; when `nonfinite` is given, those of the chunk's own columns are
-// counted.
+// counted; when `copy_to` is given, the chunk's own columns are stored there
+// (non-finite ones as 0): the frame's copy into the delay ring.
 template <int MX>
 static __device__ void row_chunk(const float* __restrict__ f, float2* __restrict__ rs, const float2* __restrict__ twx,
-                          int H, int W, int y, int x0, char* smem, unsigned long long* nonfinite) {
+                          int H, int W, int y, int x0, char* smem, unsigned long long* nonfinite,
+                          float* __restrict__ copy_to = nullptr) {
   constexpr int NP = RowShape<MX>::NP;
   constexpr int NSEG = RCX / RSEG;
   constexpr bool EVEN = (MX % 2 == 0);
@@ -55,6 +57,7 @@ static __device__ void row_chunk(const float* __restrict__ f, float2* __restrict
       bad += (i >= MX) ? 1 : 0;     // count the chunk's own columns only
     }
     s_in[i] = v;
+    if (copy_to != nullptr && i >= MX && xx < W) copy_to[(size_t)y * W + xx] = v;
   }
   for (int i = threadIdx.x; i < MX; i += blockDim.x) s_tw[i] = twx[i];
   if (nonfinite) {

@@ -477,12 +477,10 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   float* slot = c->ring + HW * (size_t)(c->t % c->nring);
   EventPair ev{};
   hipError_t e;
-  timed_begin(c, 2, &ev);
-  e = rmdf::launch_ingest(frame, slot, (long long)HW, c->nonfinite, c->stream);
-  timed_end(c, &ev);
-  if (e != hipSuccess) return hip_fail(c, e, "ingest launch");
+  // row sliding DFT straight from the caller's frame; the same kernel stores
+  // the frame (non-finite samples zeroed and counted) into the delay ring
   timed_begin(c, 1, &ev);
-  e = rmdf::launch_row(c->MX, slot, c->rs, c->twx, c->H, c->W, c->stream);
+  e = rmdf::launch_row(c->MX, frame, c->rs, c->twx, c->H, c->W, slot, c->nonfinite, c->stream);
   timed_end(c, &ev);
   if (e != hipSuccess) return hip_fail(c, e, "row kernel launch");
 

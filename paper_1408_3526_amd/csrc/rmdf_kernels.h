@@ -57,7 +57,10 @@ int pixel_block_columns(int mx, int my, int mz);
 // default rows per work tile for an H x W frame
 int auto_tile_rows(int H, int W, int block_columns);
 hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s);
-hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s);
+// row sliding DFT of the frame f; also copies f into the delay-ring slot
+// (non-finite samples zeroed and counted in *nonfinite)
+hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, float* slot,
+                      unsigned long long* nonfinite, hipStream_t s);
 // layout: 0 generic observer state [plane][ky][kz]; 1 wave-per-anchor 16x16x8
 // observer state; 2 ring of 2-D spectra [slot][plane][ky] whose newest frame
 // is `newest` (slot newest mod Mz)
@@ -71,6 +74,5 @@ int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anch
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 // list: [1 + H*W] ints of scratch (count, then the confident anchors)
 hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);
-hipError_t launch_ingest(const float* in, float* slot, long long n, unsigned long long* nonfinite, hipStream_t s);
 
 }  // namespace rmdf

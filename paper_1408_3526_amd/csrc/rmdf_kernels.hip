@@ -2,9 +2,10 @@
 // prediction-error filter (Kennedy, arXiv:1408.3526).
 //
 // Per frame (all on one stream):
-//   k_ingest  : frame -> delay ring slot, non-finite samples -> 0 (counted)
 //   k_row     : row sliding DFT (comb x(n) - x(n-M) into resonators w^k,
-//               Sec. 1, eq. 6-7) -> row spectra rs[y][x][plane]
+//               Sec. 1, eq. 6-7) -> row spectra rs[y][x][plane]; also stores
+//               the frame into its delay-ring slot (non-finite samples -> 0,
+//               counted)
 //   k_pixel   : per anchor (x, y): column sliding DFT, temporal deadbeat
 //               observer (state streamed once), high-pass + Hann + power
 //               spectrum (eq. 9), autocorrelation on the candidate grid at
@@ -25,31 +26,19 @@
 namespace rmdf {
 
 // ---------------------------------------------------------------------------
-// Ingest: copy the caller's frame into the delay ring, zero non-finite values.
-__global__ void __launch_bounds__(256) k_ingest(const float* __restrict__ in, float* __restrict__ ring_slot,
-                                                long long n, unsigned long long* __restrict__ nonfinite) {
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  int bad = 0;
-  for (; i < n; i += (long long)gridDim.x * blockDim.x) {
-    float v = in[i];
-    if (!isfinite(v)) { v = 0.0f; bad = 1; }
-    ring_slot[i] = v;
-  }
-  // one atomic per wave that saw a non-finite sample
-  unsigned long long m = __ballot(bad);
-  if (m && (threadIdx.x & 63) == __ffsll((long long)m) - 1) atomicAdd(nonfinite, (unsigned long long)__popcll(m));
-}
-
-// ---------------------------------------------------------------------------
 // Row sliding DFT.  Block = (row y, chunk of RCX columns).  Each (plane,
 // segment) thread seeds its resonators with the direct DFT of the Mx samples
 // before the segment, then runs the comb/resonator recursion across RSEG
 // columns; results are staged in LDS and written coalesced.
+// The single-stream push reads the caller's frame here directly: each block
+// also copies its own columns (non-finite samples zeroed and counted) into
+// the delay-ring slot, so the frame is read once per push.
 template <int MX>
 __global__ void __launch_bounds__(256) k_row(const float* __restrict__ f, float2* __restrict__ rs,
-                                             const float2* __restrict__ twx, int H, int W) {
+                                             const float2* __restrict__ twx, int H, int W, float* __restrict__ slot,
+                                             unsigned long long* __restrict__ nonfinite) {
   __shared__ __align__(16) char smem[RowShape<MX>::SMEM];
-  row_chunk<MX>(f, rs, twx, H, W, blockIdx.y, blockIdx.x * RCX, smem, nullptr);
+  row_chunk<MX>(f, rs, twx, H, W, blockIdx.y, blockIdx.x * RCX, smem, nonfinite, slot);
 }
 
 template <int MX, int MY, int MZ>
@@ -121,9 +110,10 @@ static hipError_t launch_pixel_t(const PixArgs& a, hipStream_t s) {
 }
 
 template <int MX>
-static hipError_t launch_row_t(const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s) {
+static hipError_t launch_row_t(const float* f, float2* rs, const float2* twx, int H, int W, float* slot,
+                               unsigned long long* nonfinite, hipStream_t s) {
   dim3 grid((W + RCX - 1) / RCX, H);
-  hipLaunchKernelGGL((k_row<MX>), grid, dim3(256), 0, s, f, rs, twx, H, W);
+  hipLaunchKernelGGL((k_row<MX>), grid, dim3(256), 0, s, f, rs, twx, H, W, slot, nonfinite);
   return hipGetLastError();
 }
 
@@ -166,10 +156,11 @@ hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s)
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, hipStream_t s) {
-  if (mx == 8) return launch_row_t<8>(f, rs, twx, H, W, s);
-  if (mx == 16) return launch_row_t<16>(f, rs, twx, H, W, s);
-  if (mx == 9) return launch_row_t<9>(f, rs, twx, H, W, s);
+hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, float* slot,
+                      unsigned long long* nonfinite, hipStream_t s) {
+  if (mx == 8) return launch_row_t<8>(f, rs, twx, H, W, slot, nonfinite, s);
+  if (mx == 16) return launch_row_t<16>(f, rs, twx, H, W, slot, nonfinite, s);
+  if (mx == 9) return launch_row_t<9>(f, rs, twx, H, W, slot, nonfinite, s);
   return hipErrorInvalidValue;
 }
 
@@ -185,12 +176,5 @@ hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, cons
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_ingest(const float* in, float* slot, long long n, unsigned long long* nonfinite, hipStream_t s) {
-  long long blocks = (n + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_ingest, dim3((unsigned)blocks), dim3(256), 0, s, in, slot, n, nonfinite);
-  return hipGetLastError();
-}
 
 }  // namespace rmdf
