@@ -424,7 +424,7 @@ def main():
                     help="only run a 1 GiB device copy (the reference kernel for the PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the per-pixel state shards by row strips; see the design notes)", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

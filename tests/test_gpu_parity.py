@@ -282,7 +282,7 @@ def test_paper_scene_figure1_on_gpu():
     g = scenes.grid(-2, 2, 0.25)
     res = run_gpu(sc.frames, (9, 9, 5), g, g)
     # the occluding target corrupts the autocorrelation along its track (the
-    # smoother remembers it): judge the clutter velocity away from the track,
+    # smoother remembers it): check the clutter velocity away from the track,
     # in anchor coordinates (pixel + m'), and away from the zero-padded border
     ys, xs = np.mgrid[0:64, 0:64]
     keep = np.ones((64, 64), bool)
