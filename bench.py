@@ -425,7 +425,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path "
-              "(the per-pixel state shards by row strips; see the design notes)", file=sys.stderr)
+              "(the per-pixel state would shard by horizontal strips of rows, each with a halo of My - 1 rows)",
+              file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
