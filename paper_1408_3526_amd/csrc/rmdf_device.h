@@ -189,16 +189,19 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
   float2* s_t = s_u + PPB * NXH * MY;                  // [PPB][NXH][NVY_MAX]
   const int nvx = a.nvx, nvy = a.nvy, nv = a.nv;
 
-  // Column sliding DFT: seed with the direct DFT of the My rows above y0.
+  // Column sliding DFT: seed with the direct DFT of the My rows above y0
+  // (rows above the frame count as zero).  All My loads are issued before the
+  // sum, so a tile start costs one memory latency, not My of them.
   float2 acol = make_float2(0.f, 0.f);
   if (col_ok) {
+    float2 v[MY];
+#pragma unroll
     for (int m = 0; m < MY; ++m) {
       const int yy = y0 - 1 - m;
-      if (yy < 0) break;
-      const float2 v = a.rs[((size_t)yy * a.W + x) * NP + p];
-      const float2 w = s_twy[(ky * m) % MY];
-      acol = cadd(acol, cmul(w, v));
+      v[m] = (yy >= 0) ? a.rs[((size_t)yy * a.W + x) * NP + p] : make_float2(0.f, 0.f);
     }
+#pragma unroll
+    for (int m = 0; m < MY; ++m) acol = cadd(acol, cmul(s_twy[(ky * m) % MY], v[m]));
   }
   const float2 wy = s_twy[ky % MY];
 

@@ -318,12 +318,23 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
   const float2* rsB = a.rs + (size_t)x * 8 + pB;
 
   // column sliding DFT seeded with the 16 rows above the tile (Horner form of
-  // the direct DFT: the same resonator run over those rows)
+  // the direct DFT: the same resonator run over those rows; rows above the
+  // frame are zero).  The 16 loads are issued before the recursion, so a tile
+  // start costs one memory latency.
   float2 acA = f2(0.f, 0.f), acB = f2(0.f, 0.f);
-  for (int yy = max(0, y0 - MY); yy < y0; ++yy) {
-    const float2 vA = rsA[(size_t)yy * rstride], vB = rsB[(size_t)yy * rstride];
-    acA = f2(wy.x * acA.x - wy.y * acA.y + vA.x, wy.x * acA.y + wy.y * acA.x + vA.y);
-    acB = f2(wy.x * acB.x - wy.y * acB.y + vB.x, wy.x * acB.y + wy.y * acB.x + vB.y);
+  {
+    float2 sA[MY], sB[MY];
+#pragma unroll
+    for (int i = 0; i < MY; ++i) {
+      const int yy = y0 - MY + i;
+      sA[i] = (yy >= 0) ? rsA[(size_t)yy * rstride] : f2(0.f, 0.f);
+      sB[i] = (yy >= 0) ? rsB[(size_t)yy * rstride] : f2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < MY; ++i) {
+      acA = f2(wy.x * acA.x - wy.y * acA.y + sA[i].x, wy.x * acA.y + wy.y * acA.x + sA[i].y);
+      acB = f2(wy.x * acB.x - wy.y * acB.y + sB[i].x, wy.x * acB.y + wy.y * acB.x + sB[i].y);
+    }
   }
 
   // Rows are software-pipelined: the observer state and row-spectrum samples
