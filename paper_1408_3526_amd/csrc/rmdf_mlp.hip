@@ -19,6 +19,7 @@ namespace mlp {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BK = 64;
 constexpr int LDSK = BK + 8;   // bf16 per LDS row (144 B): rows 16-byte aligned, banks spread
@@ -63,12 +64,23 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restric
   // so each row's BK values (128 B) are read as one contiguous run
   constexpr int KP = BK / 8;                 // pieces per row
   constexpr int LA = BM * KP / 256, LB = BN_ * KP / 256;
+  // with a single column of tiles every row of A is read exactly once: stream
+  // it past the caches (B, read by every tile, stays cached)
+  const bool a_once = (gridDim.x == 1);
   auto load = [&](int k0, uint4 (&va)[LA], uint4 (&vb)[LB]) {
 #pragma unroll
     for (int t = 0; t < LA; ++t) {
       const int q = tid + 256 * t, r = q / KP, gk = k0 + (q % KP) * 8;
       va[t] = make_uint4(0, 0, 0, 0);
-      if (m0 + r < M && gk < K) va[t] = *reinterpret_cast<const uint4*>(A + (size_t)(m0 + r) * lda + gk);
+      if (m0 + r < M && gk < K) {
+        const uint4* src = reinterpret_cast<const uint4*>(A + (size_t)(m0 + r) * lda + gk);
+        if (a_once) {
+          const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(src));
+          va[t] = make_uint4(v.x, v.y, v.z, v.w);
+        } else {
+          va[t] = *src;
+        }
+      }
     }
 #pragma unroll
     for (int t = 0; t < LB; ++t) {

@@ -44,6 +44,7 @@ static __device__ __forceinline__ float2 f2(float x, float y) { return make_floa
 #define RMDF_LDS __attribute__((address_space(3)))
 #define RMDF_GLOBAL __attribute__((address_space(1)))
 typedef float v2f __attribute__((ext_vector_type(2)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef RMDF_LDS v2f lds_v2;
 typedef RMDF_LDS v4f lds_v4;
@@ -563,7 +564,8 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
         u.y = to_bf16(L[2] - mean) | ((unsigned int)to_bf16(L[3] - mean) << 16);
         u.z = to_bf16(L[4] - mean) | ((unsigned int)to_bf16(L[5] - mean) << 16);
         u.w = to_bf16(L[6] - mean) | ((unsigned int)to_bf16(L[7] - mean) << 16);
-        *reinterpret_cast<uint4*>(fp + (kx * MY + ky) * MZ) = u;
+        // streamed: read once, by the network's first layer after the frame
+        __builtin_nontemporal_store(v4u{u.x, u.y, u.z, u.w}, reinterpret_cast<v4u*>(fp + (kx * MY + ky) * MZ));
       };
       put8(pA, PA);
       put8(pB, PB);
