@@ -21,7 +21,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BK = 64;
+constexpr int BK = 64;
 constexpr int LDSK = BK + 8;   // bf16 per LDS row (144 B): rows 16-byte aligned, banks spread
 
 enum : int { EPI_NONE = 0, EPI_RELU = 1, EPI_RELU_GRAD = 2 };
@@ -38,32 +38,35 @@ __device__ __forceinline__ float bf16_float(unsigned short b) { return __uint_as
 // C = epi(A . B^T + bias).  A: M x K (lda), B: N x K (ldb), BF16 row-major,
 // K contiguous.  Output FP32 (Cf) and/or BF16 (Cb), row-major ldc.
 // EPI_RELU_GRAD multiplies by (aux[m][n] > 0) where aux is BF16 (ldaux).
-// Tile BM x BN_ (BN_ = 64 or 128), four wavefronts in a 2 x 2 arrangement,
-// each owning 32 x (BN_ / 2) of C as BN_ / 64 MFMA 32x32 accumulators.  With
-// BN_ = 128 a layer of 128 outputs reads its input rows once.  K advances
-// 64 at a time (128 contiguous bytes per row); the next K slice's global loads
-// are issued before the current slice's MFMAs.
-template <int BN_>
+// Tile BM_ x BN_ (64 or 128 each), four wavefronts in a 2 x 2 arrangement,
+// each owning (BM_ / 2) x (BN_ / 2) of C as (BM_ / 64) x (BN_ / 64) MFMA
+// 32x32 accumulators.  With BN_ = 128 a layer of 128 outputs reads its input
+// rows once; BM_ = 128 halves the re-reads of B (from L2) per row of A.  K
+// advances 64 at a time (128 contiguous bytes per row); the next K slice's
+// global loads are issued before the current slice's MFMAs.
+template <int BM_, int BN_>
 __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restrict__ A, int lda,
                                                  const unsigned short* __restrict__ B, int ldb, int M, int N, int K,
                                                  const float* __restrict__ bias, int epi,
                                                  const unsigned short* __restrict__ aux, int ldaux,
                                                  float* __restrict__ Cf, unsigned short* __restrict__ Cb, int ldc) {
-  constexpr int NB = BN_ / 64;           // B rows per loader thread, accumulators per wavefront
-  __shared__ __align__(16) unsigned short sA[BM * LDSK];
+  constexpr int NB = BN_ / 64, MA = BM_ / 64;   // accumulator columns and rows per wavefront
+  __shared__ __align__(16) unsigned short sA[BM_ * LDSK];
   __shared__ __align__(16) unsigned short sB[BN_ * LDSK];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = wv >> 1, wn = wv & 1;
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN_;
-  f32x16 acc[NB];
+  const int m0 = blockIdx.y * BM_, n0 = blockIdx.x * BN_;
+  f32x16 acc[MA][NB];
 #pragma unroll
-  for (int t = 0; t < NB; ++t)
+  for (int u = 0; u < MA; ++u)
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[t][i] = 0.f;
+    for (int t = 0; t < NB; ++t)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[u][t][i] = 0.f;
   // loader: 8 bf16 (16 B) per piece; piece q -> row q / (BK / 8), k = (q % (BK / 8)) * 8,
   // so each row's BK values (128 B) are read as one contiguous run
   constexpr int KP = BK / 8;                 // pieces per row
-  constexpr int LA = BM * KP / 256, LB = BN_ * KP / 256;
+  constexpr int LA = BM_ * KP / 256, LB = BN_ * KP / 256;
   // with a single column of tiles every row of A is read exactly once: stream
   // it past the caches (B, read by every tile, stays cached)
   const bool a_once = (gridDim.x == 1);
@@ -108,23 +111,28 @@ __global__ void __launch_bounds__(256) k_gemm_nt(const unsigned short* __restric
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int r = lane & 31, kq = kk + (lane >> 5) * 8;
-      const bf16x8 a = *reinterpret_cast<const bf16x8*>(&sA[(wm * 32 + r) * LDSK + kq]);
+      bf16x8 a[MA];
+#pragma unroll
+      for (int u = 0; u < MA; ++u) a[u] = *reinterpret_cast<const bf16x8*>(&sA[(wm * 32 * MA + 32 * u + r) * LDSK + kq]);
 #pragma unroll
       for (int t = 0; t < NB; ++t) {
         const bf16x8 b = *reinterpret_cast<const bf16x8*>(&sB[(wn * 32 * NB + 32 * t + r) * LDSK + kq]);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[t], 0, 0, 0);
+#pragma unroll
+        for (int u = 0; u < MA; ++u) acc[u][t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[u], b, acc[u][t], 0, 0, 0);
       }
     }
   }
   // D layout: column = lane % 32; row = (i / 4) * 8 + (lane / 32) * 4 + i % 4
 #pragma unroll
+  for (int u = 0; u < MA; ++u)
+#pragma unroll
   for (int t = 0; t < NB; ++t) {
     const int col = n0 + wn * 32 * NB + 32 * t + (lane & 31);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int row = m0 + wm * 32 + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
+      const int row = m0 + wm * 32 * MA + 32 * u + (i >> 2) * 8 + (lane >> 5) * 4 + (i & 3);
       if (row < M && col < N) {
-        float v = acc[t][i] + (bias ? bias[col] : 0.f);
+        float v = acc[u][t][i] + (bias ? bias[col] : 0.f);
         if (epi == EPI_RELU) v = v > 0.f ? v : 0.f;
         else if (epi == EPI_RELU_GRAD) v = (bf16_float(aux[(size_t)row * ldaux + col]) > 0.f) ? v : 0.f;
         if (Cf) Cf[(size_t)row * ldc + col] = v;
@@ -289,16 +297,24 @@ rmdf_status rmdf_mlp_gemm_nt(const void* A, int lda, const void* B, int ldb, int
   if (!A || !B || M < 1 || N < 1 || K < 1 || (K % 8) || (lda % 8) || (ldb % 8) || (!Cf && !Cb) || epi < 0 || epi > 2 ||
       (epi == EPI_RELU_GRAD && !aux))
     return RMDF_E_INVAL;
-  if (N >= 128) {
-    dim3 grid((N + 127) / 128, (M + BM - 1) / BM);
-    hipLaunchKernelGGL(k_gemm_nt<128>, grid, dim3(256), 0, S(stream), (const unsigned short*)A, lda,
-                       (const unsigned short*)B, ldb, M, N, K, bias, epi, (const unsigned short*)aux, ldaux, Cf,
-                       (unsigned short*)Cb, ldc);
+  // 128-row tiles where there are rows enough to fill the chip twice over
+  const bool tall = (long long)M >= 128LL * 512;
+  const unsigned short* a = (const unsigned short*)A;
+  const unsigned short* b = (const unsigned short*)B;
+  const unsigned short* x = (const unsigned short*)aux;
+  unsigned short* cb = (unsigned short*)Cb;
+  if (N >= 128 && tall) {
+    dim3 grid((N + 127) / 128, (M + 127) / 128);
+    hipLaunchKernelGGL((k_gemm_nt<128, 128>), grid, dim3(256), 0, S(stream), a, lda, b, ldb, M, N, K, bias, epi, x,
+                       ldaux, Cf, cb, ldc);
+  } else if (N >= 128) {
+    dim3 grid((N + 127) / 128, (M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm_nt<64, 128>), grid, dim3(256), 0, S(stream), a, lda, b, ldb, M, N, K, bias, epi, x,
+                       ldaux, Cf, cb, ldc);
   } else {
-    dim3 grid((N + 63) / 64, (M + BM - 1) / BM);
-    hipLaunchKernelGGL(k_gemm_nt<64>, grid, dim3(256), 0, S(stream), (const unsigned short*)A, lda,
-                       (const unsigned short*)B, ldb, M, N, K, bias, epi, (const unsigned short*)aux, ldaux, Cf,
-                       (unsigned short*)Cb, ldc);
+    dim3 grid((N + 63) / 64, (M + 63) / 64);
+    hipLaunchKernelGGL((k_gemm_nt<64, 64>), grid, dim3(256), 0, S(stream), a, lda, b, ldb, M, N, K, bias, epi, x,
+                       ldaux, Cf, cb, ldc);
   }
   return st_of(hipGetLastError());
 }

@@ -23,7 +23,8 @@ def _bf(a):
     return torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).cuda()
 
 
-@pytest.mark.parametrize("M,N,K", [(100, 70, 48), (64, 64, 32), (4096, 128, 1152), (37, 130, 200)])
+@pytest.mark.parametrize("M,N,K", [(100, 70, 48), (64, 64, 32), (4096, 128, 1152), (37, 130, 200),
+                                   (65600, 128, 256), (66001, 192, 64)])
 @pytest.mark.parametrize("epi", [0, 1, 2])
 def test_gemm_nt_matches_reference(M, N, K, epi):
     b = _b()
