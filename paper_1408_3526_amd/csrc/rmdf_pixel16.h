@@ -181,10 +181,12 @@ static __device__ __forceinline__ float2 hann_x_power(const lds_v2* s_b, int ky,
 
 // One work tile: 4 adjacent anchor columns starting at 4*xb (one per
 // wavefront), rows [yb*TY, yb*TY + TY).  All 256 threads must call it.
-static __device__ __forceinline__ unsigned short to_bf16(float f) {
-  unsigned int u = __float_as_uint(f);
-  u += 0x7fffu + ((u >> 16) & 1u);      // round to nearest even (finite inputs)
-  return (unsigned short)(u >> 16);
+// Two floats to BF16 (round to nearest even), packed lo | hi << 16: one
+// v_cvt_pk_bf16_f32 on gfx950.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+static __device__ __forceinline__ unsigned int pack_bf16x2(float lo, float hi) {
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(unsigned int, v);
 }
 
 // cos(m pi / 8) and sin(m pi / 8) for integer m.
@@ -560,10 +562,10 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
       unsigned short* fp = a.feat + pix * (NXH * MY * MZ);
       auto put8 = [&](int kx, const float* L) {
         uint4 u;
-        u.x = to_bf16(L[0] - mean) | ((unsigned int)to_bf16(L[1] - mean) << 16);
-        u.y = to_bf16(L[2] - mean) | ((unsigned int)to_bf16(L[3] - mean) << 16);
-        u.z = to_bf16(L[4] - mean) | ((unsigned int)to_bf16(L[5] - mean) << 16);
-        u.w = to_bf16(L[6] - mean) | ((unsigned int)to_bf16(L[7] - mean) << 16);
+        u.x = pack_bf16x2(L[0] - mean, L[1] - mean);
+        u.y = pack_bf16x2(L[2] - mean, L[3] - mean);
+        u.z = pack_bf16x2(L[4] - mean, L[5] - mean);
+        u.w = pack_bf16x2(L[6] - mean, L[7] - mean);
         // streamed: read once, by the network's first layer after the frame
         __builtin_nontemporal_store(v4u{u.x, u.y, u.z, u.w}, reinterpret_cast<v4u*>(fp + (kx * MY + ky) * MZ));
       };
