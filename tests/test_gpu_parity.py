@@ -385,6 +385,28 @@ def test_state_errors():
     f.close()
 
 
+def test_kernel_timing_mask():
+    """rmdf_set_timing's mask: only the selected kernels are bracketed."""
+    b = _binding()
+    g = scenes.grid(-2, 2, 1.0)
+    f = b.Filter(40, 48, 16, 16, 8, g, g)
+    fr = torch.from_numpy((np.random.default_rng(0).normal(size=(6, 40, 48)) + 10).astype(np.float32)).cuda()
+    f.set_timing(kernels=[0])
+    for t in range(3):
+        f.push_frame(fr[t])
+    ms0, n0 = f.kernel_time(0)
+    ms1, n1 = f.kernel_time(1)
+    assert n0 == 3 and ms0 > 0 and n1 == 0 and ms1 == 0
+    f.set_timing(True)
+    for t in range(3, 6):
+        f.push_frame(fr[t])
+    assert f.kernel_time(0)[1] == 3 and f.kernel_time(1)[1] == 3
+    f.set_timing(False)
+    f.push_frame(fr[0])
+    assert f.kernel_time(0)[1] == 0
+    f.close()
+
+
 def test_auto_tile_rows():
     """Default tile height: 32 rows where the frame has >= 2048 work tiles,
     halved (down to 1) on smaller frames; an explicit value is kept."""
