@@ -399,9 +399,31 @@ def cpu_baseline(frames, wl, g, budget_frames=18, crop=(128, 160)):
     oracle.run(cfg, sub)
     dt = time.perf_counter() - t0
     n = sub.shape[0] * sub.shape[1] * sub.shape[2]
-    return {"value": n / dt, "unit": "pixel-frames/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    # one thread, on a smaller sample of the same frames (a 48x64 crop, 8 frames)
+    one = np.ascontiguousarray(frames[:8, :48, :64])
+    cfg1 = oracle.Cfg(H=one.shape[1], W=one.shape[2], Mx=wl["M"][0], My=wl["M"][1], Mz=wl["M"][2], gx=g, gy=g)
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.run(cfg1, one)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(cores)
+    n1 = one.shape[0] * one.shape[1] * one.shape[2]
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return {"value": n / dt, "unit": "pixel-frames/s", "cores": cores, "kind": "oracle",
+            "host": {"cpu": model, "usable_cpus": len(os.sched_getaffinity(0))},
             "sample": "%dx%d crop of the workload's frames, %d frames (%d pixel-frames, %.1f s)"
-                      % (sub.shape[2], sub.shape[1], sub.shape[0], n, dt)}
+                      % (sub.shape[2], sub.shape[1], sub.shape[0], n, dt),
+            "one_thread": {"value": n1 / dt1, "cores": 1,
+                           "sample": "%dx%d crop, %d frames (%d pixel-frames, %.1f s)"
+                                     % (one.shape[2], one.shape[1], one.shape[0], n1, dt1)}}
 
 
 def main():

@@ -45,7 +45,8 @@ def build(force: bool = True) -> str:
 def lib():
     global _LIB
     if _LIB is None:
-        if not os.path.exists(_SO):
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < max(os.path.getmtime(_SRC), os.path.getmtime(
+                os.path.join(_HERE, "rmdf_oracle.h"))):
             build(force=True)
         L = ctypes.CDLL(_SO)
         dp = ctypes.POINTER(ctypes.c_double)
@@ -61,6 +62,8 @@ def lib():
         L.orc_run.restype = ctypes.c_int
         L.orc_run.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p] + [ctypes.c_void_p] * 9
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         L.orc_peak_vertex.restype = ctypes.c_double
         L.orc_peak_vertex.argtypes = [ctypes.c_double] * 6
         L.orc_refine.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
@@ -269,3 +272,8 @@ def pixel_series(cfg: Cfg, frames: np.ndarray, x: int, y: int, T: int | None = N
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops (timing runs only)."""
+    lib().orc_set_threads(int(n))

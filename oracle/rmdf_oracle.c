@@ -24,6 +24,14 @@ int orc_threads(void) {
 #endif
 }
 
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* w_M^k = exp(+j 2 pi k / M), the resonator pole of the sliding DFT (eq. 7). */
 static double complex twiddle(int M, long long k) {
   long long r = k % M;

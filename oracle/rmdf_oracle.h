@@ -105,6 +105,8 @@ int orc_run(const orc_cfg *c, int T, const float *frames,
 
 /* Number of OpenMP threads the pipeline uses (0 if built without OpenMP). */
 int orc_threads(void);
+/* Threads for the next parallel regions (n > 0); timing only. */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
