@@ -292,8 +292,10 @@ rmdf_status rmdf_batch_set_tiles(rmdf_batch *b, int s, int tile_rows);
  * 1: one persistent kernel for the 16x16x8 wave-per-anchor, 8x8x4 and 9x9x5
  *    families, their work items interleaved in proportion;
  * 2: as 0, with the 8x8x4 and 9x9x5 kernels on a parallel branch of the
- *    graph (they may run beside the 16x16x8 kernel).
- * The results do not depend on the schedule.  The autotuner tries all three. */
+ *    graph (they may run beside the 16x16x8 kernel);
+ * 3: as 2, the parallel branch's kernels launched first.
+ * Other values: RMDF_E_INVAL.  The results do not depend on the schedule.
+ * The autotuner tries all four. */
 rmdf_status rmdf_batch_set_schedule(rmdf_batch *b, int schedule);
 /* Pick rows per tile for each size class and the persistent grid size by
  * timing whole steps (iters timed launches per candidate).  The streams

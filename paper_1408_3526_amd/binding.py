@@ -412,7 +412,8 @@ class Batch:
 
     def set_schedule(self, schedule: int):
         """0 one kernel per tile family, 1 one mixed kernel, 2 small families
-        on a parallel graph branch (rmdf_batch_set_schedule)."""
+        on a parallel graph branch, 3 as 2 with the small families launched
+        first (rmdf_batch_set_schedule)."""
         _bcheck(lib().rmdf_batch_set_schedule(self.b, int(schedule)), self.b)
 
     def autotune(self, iters: int = 5) -> str:

@@ -169,10 +169,11 @@ struct rmdf_batch {
   int grid_mult = 1;                 // persistent workgroups per resident slot
   // schedule of the pixel tiles: 0 one kernel per family, one after another;
   // 1 one kernel for all families (k_batch_mixed); 2 one kernel per family,
-  // the small families on a second graph branch beside the 16x16x8 kernels
+  // the small families on a second graph branch beside the 16x16x8 kernels;
+  // 3 as 2, the small families' kernels launched first
   int schedule = 0;
   int mixed_blocks = 0;
-  hipStream_t side = nullptr;        // second capture stream (schedule 2)
+  hipStream_t side = nullptr;        // second capture stream (schedules 2, 3)
   hipEvent_t fork = nullptr, join = nullptr;
   // device
   RowDesc* d_row = nullptr;
@@ -314,16 +315,22 @@ static hipError_t rebuild(rmdf_batch* b) {
   if (mixed && b->mixed_blocks > 0)
     hipLaunchKernelGGL(k_batch_mixed, dim3(b->mixed_blocks), dim3(256), 0, b->stream, b->d_pix,
                        (const int4*)b->d_items + (iv.size() - n_mixed), n_mixed, bs);
-  // schedule 2: fork after the row pass, the small families on the side branch
-  const bool branch = (b->schedule == 2) && (b->blocks[KIND_884] > 0 || b->blocks[KIND_995] > 0);
+  // schedules 2 and 3: fork after the row pass, the small families on the
+  // side branch (3: captured, hence dispatched, before the large families, so
+  // their workgroups are resident first and the 16x16x8 kernel's persistent
+  // workgroups take their slots as they finish)
+  const bool branch = (b->schedule >= 2) && (b->blocks[KIND_884] > 0 || b->blocks[KIND_995] > 0);
   if (branch) {
     hipEventRecord(b->fork, b->stream);
     hipStreamWaitEvent(b->side, b->fork, 0);
   }
   // per family: the largest tiles first (in mixed mode only the generic
   // 16x16x8 family, whose items open the list, on queue[KIND_16G])
-  const int order[NKIND] = {KIND_16W, KIND_16G, KIND_995, KIND_884};
-  for (int k : order) {
+  static const int largest_first[NKIND] = {KIND_16W, KIND_16G, KIND_995, KIND_884};
+  static const int small_first[NKIND] = {KIND_995, KIND_884, KIND_16W, KIND_16G};
+  const int* order = (branch && b->schedule == 3) ? small_first : largest_first;
+  for (int i = 0; i < NKIND; ++i) {
+    const int k = order[i];
     if ((mixed && in_mixed(k)) || b->blocks[k] == 0) continue;
     int first = 0;
     if (!mixed)
@@ -408,7 +415,7 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
     base += r.chunks * a.H;
   }
   b->row_blocks = base;
-  // second branch of the captured step (schedule 2); default priority
+  // second branch of the captured step (schedules 2, 3); default priority
   if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess)
@@ -496,7 +503,7 @@ rmdf_status rmdf_batch_set_tiles(rmdf_batch* b, int s, int tile_rows) {
 }
 
 rmdf_status rmdf_batch_set_schedule(rmdf_batch* b, int schedule) {
-  if (!b || schedule < 0 || schedule > 2) return bfail(b, RMDF_E_INVAL, "schedule must be 0, 1 or 2");
+  if (!b || schedule < 0 || schedule > 3) return bfail(b, RMDF_E_INVAL, "schedule must be 0, 1, 2 or 3");
   hipStreamSynchronize(b->stream);
   b->schedule = schedule;
   hipError_t e = rebuild(b);
@@ -598,7 +605,7 @@ rmdf_status rmdf_batch_autotune(rmdf_batch* b, int iters, char* report, size_t r
   b->grid_mult = best_mult;
   // schedule of the tile families
   int best_sched = b->schedule;
-  for (int sc = 0; sc < 3; ++sc) {
+  for (int sc = 0; sc < 4; ++sc) {
     if (sc == best_sched) continue;
     b->schedule = sc;
     if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
@@ -607,8 +614,9 @@ rmdf_status rmdf_batch_autotune(rmdf_batch* b, int iters, char* report, size_t r
   }
   b->schedule = best_sched;
   if (rebuild(b) != hipSuccess) return bfail(b, RMDF_E_DEVICE, "rebuild failed");
-  static const char* sched_name[3] = {"one kernel per tile family", "one kernel for all tile families",
-                                      "one kernel per tile family, small families on a parallel branch"};
+  static const char* sched_name[4] = {"one kernel per tile family", "one kernel for all tile families",
+                                      "one kernel per tile family, small families on a parallel branch",
+                                      "one kernel per tile family, small families first on a parallel branch"};
   char line[200];
   std::snprintf(line, sizeof line, "persistent workgroups per slot %d; %s; median step %.3f ms\n", best_mult,
                 sched_name[b->schedule], best_all);

@@ -22,11 +22,11 @@ def _streams():
     ]
 
 
-@pytest.mark.parametrize("tile,schedule", [(8, 0), (32, 0), (8, 1), (32, 2)])
+@pytest.mark.parametrize("tile,schedule", [(8, 0), (32, 0), (8, 1), (32, 2), (16, 3)])
 def test_batch_graph_replays_equal_eager(tile, schedule):
     """Every schedule of the tile families (one kernel per family, one mixed
-    kernel, small families on a parallel graph branch) gives the eager
-    single-stream results bit for bit."""
+    kernel, small families on a parallel graph branch, launched after or
+    before the large ones) gives the eager single-stream results bit for bit."""
     from paper_1408_3526_amd import binding
     st = _streams()
     T = 10
@@ -115,4 +115,24 @@ def test_batch_autotune_and_latency():
         b.push([d[t % 10] for d in dev])
     lat = b.latency()
     assert lat["steps"] == 5 and 0 < lat["p50_ms"] <= lat["p99_ms"]
+    b.close()
+
+
+def test_batch_rejects_bad_schedule_and_tiles():
+    """Out-of-range schedules, stream indexes and tile heights are refused
+    with RMDF_E_INVAL, and the batch stays usable."""
+    from paper_1408_3526_amd import binding
+    st = _streams()[:2]
+    b = binding.Batch(st, tile_rows=8)
+    for bad in (-1, 4):
+        with pytest.raises(binding.RmdfError) as ei:
+            b.set_schedule(bad)
+        assert ei.value.status == binding.RMDF_E_INVAL
+    for s, ty in ((2, 8), (-2, 8), (0, 0)):
+        with pytest.raises(binding.RmdfError) as ei:
+            b.set_tiles(s, ty)
+        assert ei.value.status == binding.RMDF_E_INVAL
+    b.set_schedule(3)
+    b.push([torch.from_numpy(s["frames"][0]).cuda() for s in st])
+    torch.cuda.synchronize()
     b.close()
