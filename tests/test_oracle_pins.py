@@ -436,3 +436,43 @@ def test_pixel_series_matches_run_refined(orc):
             if p["idx"][t] == r["idx"][t, y, x]:
                 assert np.abs(p["vxy"][t] - r["vxy"][t, y, x]).max() <= 1e-7
                 assert abs(p["out"][t] - r["out"][t, y, x]) <= 1e-7 * 100
+
+
+# Smoothing and argmax (Sec. 2, flow paragraph): the smoothed R obeys
+# R'_t = (1 - alpha) R_t + alpha R'_{t-1} with R'_{-1} = 0, where R_t is taken
+# here by the brute route (sample-domain autocorrelation of each frame's
+# window, eq. 10 via Wiener-Khinchin); the chosen index is the first maximum
+# of R'_t in row-major (iy, ix) order (numpy's argmax, which returns the
+# first maximum), and the velocity is the grid value at that index.
+@pytest.mark.parametrize("M,grid,alpha", [((8, 8, 4), 3, float(np.exp(-0.1))), ((8, 8, 4), 3, 0.0),
+                                          ((9, 9, 5), 2, 0.5), ((6, 5, 4), 2, 0.8)])
+def test_smoothing_recurrence_and_first_maximum(orc, M, grid, alpha):
+    rng = np.random.default_rng(21)
+    H, W, T = M[1] + 4, M[0] + 5, M[2] + 5
+    fr = (rng.normal(size=(T, H, W)) * 3 + 20).astype(np.float32)
+    g = np.arange(-grid, grid + 1, dtype=float)
+    cfg = _cfg(orc, H, W, M, gx=g, gy=g, alpha=alpha)
+    r = orc.run(cfg, fr, want_r=True, want_rs=True)
+    f64 = fr.astype(np.float64)
+    # full-window, left-border and top-border anchors
+    for x, y in [(W - 1, H - 1), (M[0] + 1, M[1]), (2, H - 2), (W - 3, 1)]:
+        prev = np.zeros(len(g) ** 2)
+        for t in range(T):
+            s = brute.flow_block(brute.block(f64, x, y, t, M))
+            R = np.array([brute.autocorr_cyclic(s, (lx, ly, 1)) for ly in g for lx in g])
+            tol = 1e-12 * max(np.sum(s * s), 1e-300)
+            assert np.abs(r["r_all"][t, y, x] - R).max() <= tol
+            want = (1.0 - alpha) * R + alpha * prev
+            assert np.abs(r["rs_all"][t, y, x] - want).max() <= 4 * tol + 1e-12 * np.abs(want).max()
+            prev = r["rs_all"][t, y, x]
+    rs = r["rs_all"]
+    assert np.array_equal(r["idx"], np.argmax(rs, axis=-1))
+    nvx = len(g)
+    assert np.array_equal(r["vxy"][..., 0], g[r["idx"] % nvx])
+    assert np.array_equal(r["vxy"][..., 1], g[r["idx"] // nvx])
+    # exact ties: all-zero frames make every R' exactly 0, so the first
+    # maximum is index 0 and the velocity the grid's first candidate
+    z = orc.run(cfg, np.zeros_like(fr), want_rs=True)
+    assert np.all(z["rs_all"] == 0.0)
+    assert np.all(z["idx"] == 0)
+    assert np.all(z["vxy"] == g[0])
