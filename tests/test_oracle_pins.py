@@ -476,3 +476,31 @@ def test_smoothing_recurrence_and_first_maximum(orc, M, grid, alpha):
     assert np.all(z["rs_all"] == 0.0)
     assert np.all(z["idx"] == 0)
     assert np.all(z["vxy"] == g[0])
+
+
+# The filter uses the velocity estimated at the same anchor in the same frame
+# (Sec. 1: velocity estimation and filtering per pixel and frame).  On a scene
+# whose velocity changes half-way through, every output of the search mode
+# equals the delayed input minus the direct convolution of eq. (1) at that
+# frame's own chosen velocity.
+@pytest.mark.parametrize("M", [(8, 8, 4), (9, 9, 5)])
+def test_filter_uses_the_same_frames_velocity(orc, M):
+    T, H, W = 2 * M[2] + 6, M[1] + 6, M[0] + 7
+    a = scenes.translate_scene(31, H=H, W=W, T=T, v=(1, -1), n_targets=0, noise_sigma=0.05).frames
+    b = scenes.translate_scene(31, H=H, W=W, T=T, v=(-2, 1), n_targets=0, noise_sigma=0.05).frames
+    fr = np.concatenate([a[:T // 2], b[T // 2:]]).astype(np.float32)
+    g = np.arange(-3.0, 4.0)
+    cfg = _cfg(orc, H, W, M, gx=g, gy=g)
+    r = orc.run(cfg, fr)
+    f64 = fr.astype(np.float64)
+    changed = 0
+    for t in range(T):
+        for (x, y) in [(W - 1, H - 1), (M[0] + 2, M[1] + 1), (3, H - 2)]:
+            v = tuple(r["vxy"][t, y, x])
+            if t > 0 and v != tuple(r["vxy"][t - 1, y, x]):
+                changed += 1
+            ts, xs, ys = t - cfg.dt, x - cfg.dx, y - cfg.dy
+            delayed = f64[ts, ys, xs] if (ts >= 0 and xs >= 0 and ys >= 0) else 0.0
+            ihat = brute.background_eq1(f64, x, y, t, M, (cfg.Bx, cfg.By), (cfg.dx, cfg.dy, cfg.dt), v)
+            assert abs(r["out"][t, y, x] - (delayed - ihat)) <= 1e-10 * np.abs(f64).max() * np.prod(M)
+    assert changed > 0          # the check covers frames where the chosen velocity moves
