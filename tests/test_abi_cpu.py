@@ -61,8 +61,9 @@ def _create(L, H=32, W=32, M=(8, 8, 4), gx=(0.0, 1.0), gy=(0.0,), params=None, o
     return st, msg
 
 
-@pytest.mark.parametrize("kw", [dict(H=0), dict(W=-3), dict(M=(1, 8, 4)), dict(gx=()), dict(gx=(np.nan,)),
-                                dict(gy=tuple(range(40))), dict(out=False)])
+@pytest.mark.parametrize("kw", [dict(H=0), dict(W=-3), dict(H=65536), dict(M=(1, 8, 4)), dict(gx=()),
+                                dict(gx=(np.nan,)), dict(gy=(0.0, np.inf)), dict(gy=tuple(range(40))),
+                                dict(out=False)])
 def test_create_rejects_invalid(L, kw):
     st, msg = _create(L, **kw)
     assert st == -1 and msg

@@ -382,6 +382,16 @@ def test_state_errors():
     assert e.value.status == b.RMDF_E_INVAL
     with pytest.raises(ValueError):
         f.push_frame(torch.zeros(15, 16, device="cuda"))
+    # the binding refuses what the C ABI cannot describe, before any launch
+    with pytest.raises(TypeError):
+        f.push_frame(torch.zeros(16, 16))                                    # host memory
+    with pytest.raises(TypeError):
+        f.push_frame(torch.zeros(16, 16, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        f.push_frame(torch.zeros(16, 32, device="cuda")[:, ::2])            # not contiguous
+    with pytest.raises(ValueError):
+        f.output(torch.empty(16, 17, device="cuda"))
+    assert f.frames_pushed() == 1
     f.close()
 
 
