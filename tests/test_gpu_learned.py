@@ -201,3 +201,75 @@ def test_trained_network_against_search():
     print("search", s, "learned", l)
     assert l["residual_rms"] <= 1.05 * s["residual_rms"]
     assert l["fallback_rate"] < 1.0
+
+
+def test_sampled_learned_640x512_against_oracle(orc):
+    """Learned mode on 640x512 frames with the shipped network, the
+    configuration the benchmark times (16x16x8, 17x17 grid at 0.5 px/frame,
+    confidence threshold 0.9).  At sampled anchors of the last frame:
+    the features equal the oracle's log power spectrum; the network's outputs
+    equal the FP64 forward pass on the GPU's own BF16 features; an anchor
+    takes the network's velocity (index -2) exactly where its confidence
+    reaches 0.9 and otherwise the instantaneous search's grid maximum; the
+    output equals the oracle's filter (eq. 4 with eq. 8) at the velocity taken."""
+    import os
+
+    from paper_1408_3526_amd import learned
+    if not os.path.exists(learned.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights shipped")
+    w = np.load(learned.DEFAULT_WEIGHTS)
+    b = _b()
+    H, W, T = 512, 640, 12
+    sc = scenes.flow_scene(2203, H=H, W=W, T=T)
+    g = scenes.grid(-4, 4, 0.5)
+    f = b.Filter(H, W, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9)
+    f.set_weights(w)
+    dev = torch.from_numpy(sc.frames).cuda()
+    for t in range(T):
+        f.push_frame(dev[t])
+    rng = np.random.default_rng(17)
+    pts = [(0, 0), (W - 1, H - 1), (W - 1, 0), (0, H - 1), (15, 15), (W // 2, H // 2)]
+    pts += [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(34)]
+    xs = torch.tensor([p[0] for p in pts], device="cuda")
+    ys = torch.tensor([p[1] for p in pts], device="cuda")
+    F = f.features()[ys, xs].float().cpu().numpy().astype(np.float64)
+    vc = f.learned_output()[ys, xs].cpu().numpy()
+    vxy, idx = f.velocity()
+    vxy, idx = vxy[ys, xs].cpu().numpy(), idx[ys, xs].cpu().numpy()
+    out = f.output()[ys, xs].cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+
+    # network: FP64 forward pass on the same BF16 inputs
+    O = mlp.forward(F, mlp.unpack(w))[-1]
+    conf = 1.0 / (1.0 + np.exp(-O[:, 2]))
+    assert np.abs(vc[:, :2] - O[:, :2]).max() <= 0.02 + 0.01 * np.abs(O[:, :2]).max()
+    assert np.abs(vc[:, 2] - conf).max() <= 0.01
+    confident = vc[:, 2] >= 0.9
+    assert np.array_equal(idx == -2, confident)
+    assert np.array_equal(vxy[confident], vc[confident, :2])
+
+    cfg = orc.Cfg(H=H, W=W, Mx=16, My=16, Mz=8, gx=g, gy=g, alpha=0.0)
+    rms = float(np.sqrt(np.mean(sc.frames[T - 1].astype(np.float64) ** 2)))
+    fe = []
+    for i, (x, y) in enumerate(pts):
+        p = orc.pixel_series(cfg, sc.frames, x, y)
+        S = p["S"][-1]
+        R, P = orc.flow_R(cfg, S, want_P=True)
+        fe.append(np.abs(F[i] - mlp.features_from_P(P)) / (0.05 + 0.01 * np.abs(mlp.features_from_P(P))))
+        if not confident[i]:
+            # fallback: first maximum of the instantaneous R (ties: any near-maximal pick)
+            scale = max(np.abs(R).max(), 1e-3 * P.sum(), 1e-30)
+            assert 0 <= idx[i] < len(R)
+            assert R[idx[i]] >= R.max() - 1e-4 * scale, (x, y)
+            srt = np.sort(R)
+            if srt[-1] - srt[-2] > 1e-4 * scale:
+                assert idx[i] == int(np.argmax(R)), (x, y)
+            assert vxy[i, 0] == np.float32(g[idx[i] % len(g)]) and vxy[i, 1] == np.float32(g[idx[i] // len(g)])
+        ihat = orc.background(cfg, orc.coeffs(cfg, float(vxy[i, 0]), float(vxy[i, 1])), S)
+        ts, xd, yd = T - 1 - cfg.dt, x - cfg.dx, y - cfg.dy
+        delayed = float(sc.frames[ts, yd, xd]) if (xd >= 0 and yd >= 0) else 0.0
+        assert abs(out[i] - (delayed - ihat)) <= 1e-3 * rms, (x, y, out[i], delayed - ihat)
+    e = np.concatenate(fe)
+    assert np.quantile(e, 0.995) <= 1.0 and np.median(e) <= 0.2, (np.quantile(e, 0.995), np.median(e))
+    print("sampled anchors: %d, confident: %d" % (len(pts), int(confident.sum())))
