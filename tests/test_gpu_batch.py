@@ -136,3 +136,42 @@ def test_batch_rejects_bad_schedule_and_tiles():
     b.push([torch.from_numpy(s["frames"][0]).cuda() for s in st])
     torch.cuda.synchronize()
     b.close()
+
+
+def test_batch_full_size_streams_equal_eager():
+    """One stream of each size class of the 24-stream workload, at full size
+    (320x256 at 8x8x4, 640x512 and 1280x1024 at 16x16x8), with the tile heights
+    and schedule the autotuner picks for it: every frame's outputs, velocities
+    and indexes equal those of single-stream contexts with the same tile
+    heights, bit for bit."""
+    from paper_1408_3526_amd import binding
+    g1, g5 = scenes.grid(-4, 4, 1.0), scenes.grid(-4, 4, 0.5)
+    T = 10
+    st = [dict(H=256, W=320, M=(8, 8, 4), gx=g1, gy=g1, tile=4,
+               frames=scenes.flow_scene(101, H=256, W=320, T=T).frames),
+          dict(H=512, W=640, M=(16, 16, 8), gx=g5, gy=g5, tile=32,
+               frames=scenes.flow_scene(102, H=512, W=640, T=T).frames),
+          dict(H=1024, W=1280, M=(16, 16, 8), gx=g5, gy=g5, tile=64,
+               frames=scenes.flow_scene(103, H=1024, W=1280, T=T, n_targets=50).frames)]
+    b = binding.Batch(st)
+    for i, s in enumerate(st):
+        b.set_tiles(i, s["tile"])
+    b.set_schedule(0)
+    singles = [binding.Filter(s["H"], s["W"], *s["M"], s["gx"], s["gy"], tile_rows=s["tile"]) for s in st]
+    dev = [torch.from_numpy(s["frames"]).cuda() for s in st]
+    for t in range(T):
+        b.push([d[t] for d in dev])
+        for i, sgl in enumerate(singles):
+            sgl.push_frame(dev[i][t])
+        torch.cuda.synchronize()
+        for i, sgl in enumerate(singles):
+            o_b, v_b, i_b = b.output(i)
+            o_s = sgl.output()
+            v_s, i_s = sgl.velocity()
+            torch.cuda.synchronize()
+            assert torch.equal(o_b, o_s), (t, i)
+            assert torch.equal(v_b, v_s), (t, i)
+            assert torch.equal(i_b, i_s), (t, i)
+    for sgl in singles:
+        sgl.close()
+    b.close()

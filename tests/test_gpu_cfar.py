@@ -37,7 +37,8 @@ def check(x, guard, train, k):
 
 
 @pytest.mark.parametrize("H,W,guard,train,k", [(37, 131, 2, 4, 3.0), (1, 70, 0, 3, 2.0), (16, 64, 1, 1, 2.5),
-                                               (200, 300, 3, 13, 4.0), (5, 3, 4, 2, 1.0), (130, 17, 0, 16, 3.5)])
+                                               (200, 300, 3, 13, 4.0), (5, 3, 4, 2, 1.0), (130, 17, 0, 16, 3.5),
+                                               (512, 640, 2, 4, 4.0), (512, 640, 3, 13, 3.0)])
 def test_cfar_parity_random(H, W, guard, train, k):
     rng = np.random.default_rng(H * 7 + W)
     x = rng.normal(size=(H, W)) * 2.0 + 0.3
