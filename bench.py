@@ -26,7 +26,7 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 # counters (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter
 # reads for a plain copy of known size).  The figure only stands for the
 # kernel source it was taken on: a change to any of these files voids it.
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pixel16_640x512.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pixel16_{workload}.txt")
 KERNEL_SOURCES = ["paper_1408_3526_amd/csrc/rmdf_pixel16.h", "paper_1408_3526_amd/csrc/rmdf_pixel16.hip",
                   "paper_1408_3526_amd/csrc/rmdf_kernels.h"]
 
@@ -68,7 +68,7 @@ def measured_traffic(kname, workload):
     """HBM bytes per launch from the committed counter summary, or None when
     it is absent or was taken on another kernel, workload or source."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(TRAFFIC_FILE.format(workload=workload)) as f:
             kv = dict(line.split("=", 1) for line in (ln.strip() for ln in f) if "=" in line and not line.startswith("#"))
     except OSError:
         return None
