@@ -8,6 +8,12 @@ are row-major [out][in].  Loss for a batch of n samples with labels (lx, ly):
   t = [max(|o0 - lx|, |o1 - ly|) <= half_step]  (t is a constant).
 ``bf16=True`` rounds, as the GPU does, the inputs, the first two weight
 matrices and the stored activations/gradient rows to BF16 before use.
+
+The paper has no learned part.  The input map (log scaling, the 1e-6 max P
+floor, the mean removal) and the confidence target are choices made for this
+library: parity unpinned beyond the properties the tests check (scale
+invariance of the features, the forward pass on selection weights, gradients
+against finite differences).
 """
 from __future__ import annotations
 
