@@ -107,7 +107,8 @@ class Cfg:
     def __post_init__(self):
         # Defaults (readings of Sec. 3 for window lengths the paper does not
         # list): B = floor(3M/8), m' = floor(M/2).  For M = 9 these give the
-        # paper's B = 3 and m' = K = 4.
+        # paper's B = 3 and m' = K = 4.  Parity unpinned: they are parameter
+        # choices, and every pin passes B and m' explicitly or holds for any.
         if self.Bx is None:
             self.Bx = (3 * self.Mx) // 8
         if self.By is None:
