@@ -267,7 +267,7 @@ def main(argv=None):
     ap.add_argument("--train-seeds", type=int, default=50)
     ap.add_argument("--eval-seeds", type=int, default=10)
     ap.add_argument("--per-seq", type=int, default=40000)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=30000)
     ap.add_argument("--report", default="")
     a = ap.parse_args(argv)
 
