@@ -738,26 +738,6 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
   }
 }
 
-// Background coefficient at (kx, ky centred, kz) for a continuous velocity:
-// eq. (8) at the DFT bins (the spatial Dirichlet factors select kx' = kx,
-// ky' = ky), times sqrt(Mz) (S = sqrt(Mz) X):
-//   D_Mz(kz/Mz + phi) / sqrt(Mx My Mz) * exp(j pi [-2(kx m'x/Mx + ky m'y/My)
-//   + 2 phi (m't - Dz) - 2 kz Dz/Mz]),  phi = vx kx/Mx + vy ky/My.
-static __device__ __forceinline__ float2 coeff16(int kx, int kyc, int kz, float vx, float vy, int dx, int dy, int dt) {
-  const float Dz = 0.5f * (MZ - 1);
-  const float phi = vx * kx * (1.0f / MX) + vy * kyc * (1.0f / MY);
-  const float w = kz * (1.0f / MZ) + phi;
-  const float rw = rintf(w);
-  float D;
-  if (fabsf(w - rw) < 1e-5f) D = (((int)rw * (MZ - 1)) & 1) ? -1.f : 1.f;
-  else D = sinpif(MZ * w) / (MZ * sinpif(w));
-  const float ph = -2.f * (kx * (float)dx / MX + kyc * (float)dy / MY) + 2.f * phi * (dt - Dz) - 2.f * kz * Dz / MZ;
-  float sn, cs;
-  sincospif(ph, &sn, &cs);
-  const float g = D * 0.0625f;        // sqrt(Mz) / sqrt(Mx My Mz) = 1/16
-  return f2(g * cs, g * sn);
-}
-
 // Learned mode, second pass: one wavefront per anchor.  Where the network's
 // confidence >= thr: velocity = its (vx, vy), background estimate with eq. (8)
 // at that continuous velocity, output.  Elsewhere the wavefront leaves at once
@@ -779,13 +759,11 @@ static __device__ void finish16(const PixArgs& a, const float* ring_delayed, con
       const int p = h ? pB : pA;
       if (p > a.bx) continue;
       const float2* xc = X + st16_index(p, ky, 0);   // element kz at xc[st16_index(0, 0, kz)]
-      const float wgt = (p == 0) ? 1.f : 2.f;
+      float2 xl[MZ];
 #pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const float2 c = coeff16(p, kyc, k, vx, vy, a.dx, a.dy, a.dt);
-        const float2 xv = xc[st16_index(0, 0, k)];
-        acc += wgt * (c.x * xv.x - c.y * xv.y);
-      }
+      for (int k = 0; k < MZ; ++k) xl[k] = xc[st16_index(0, 0, k)];
+      // eq. (8) at the network's continuous velocity, as in the refined mode
+      acc += pef_plane16(xl, p, kyc, vx, vy, a.dx, a.dy, a.dt);
     }
   }
 #pragma unroll
