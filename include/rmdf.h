@@ -76,7 +76,9 @@ typedef struct {
                                < 0: exp(-1/10) (Sec. 3).  Valid: [0, 1).       */
   int velocity_mode;        /* rmdf_velocity_mode                              */
   float fixed_vx, fixed_vy; /* velocity used by RMDF_VEL_FIXED                  */
-  float conf_threshold;     /* RMDF_VEL_LEARNED: search below this confidence  */
+  float conf_threshold;     /* RMDF_VEL_LEARNED: search below this confidence;
+                               a finite value in [0, 1] (checked for every
+                               mode; default 0.9)                             */
   int tile_rows;            /* rows per work tile of the pixel kernel; 0: auto
                                (32, halved down to 1 while the frame has fewer
                                than 2048 work tiles)                           */
@@ -112,7 +114,7 @@ void rmdf_params_default(rmdf_params *p);
  * smoothed autocorrelation H*W*nvx*nvy FP32, row spectra, a (m'_t+1)-frame
  * delay ring, tables) and zeroes it.
  * Compiled window shapes: 8x8x4, 16x16x8, 9x9x5 (others: RMDF_E_UNSUPPORTED).
- * Errors: RMDF_E_INVAL (H, W < 1 or H > 65535; bad B, m', alpha; nvx, nvy outside [1, 33],
+ * Errors: RMDF_E_INVAL (H, W < 1 or H > 65535; bad B, m', alpha, conf_threshold; nvx, nvy outside [1, 33],
  * non-finite grid; unknown velocity or temporal mode; RMDF_VEL_REFINED with a
  * grid that is not strictly increasing; out == NULL), RMDF_E_UNSUPPORTED (a
  * mode the chosen kernel lacks: the learned model, write_features and the
@@ -128,17 +130,36 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt,
  * into the delay ring), then the per-pixel kernel (column sliding DFT, observer update,
  * high-pass + Hann + power spectrum, autocorrelation on the grid, smoothing,
  * argmax, velocity-tuned background estimate, output).
- * Errors: RMDF_E_INVAL (NULL), RMDF_E_DEVICE (launch failure). */
+ * Paper: the frame stream I(n) of Sec. 2 (eq. 1); the local spectrum of eq. (6)
+ * updated recursively (Sec. 1: sliding DFTs in x and y, the deadbeat observer
+ * in t); the flow estimate of eq. (9)-(10) with its first-order smoother
+ * (Sec. 2, flow paragraph); the background estimate of eq. (4) with the
+ * coefficients of eq. (8).
+ * The frame is read during the call's kernels only (the caller keeps
+ * ownership).  Every argument and state check comes before the first launch,
+ * so a refused push changes nothing: not the frame count, the delay ring nor
+ * the non-finite counter.  Frames smaller than the window are accepted (the
+ * samples outside the frame count as zero).
+ * Errors: RMDF_E_INVAL (NULL), RMDF_E_STATE (learned mode without weights),
+ * RMDF_E_DEVICE (launch failure). */
 rmdf_status rmdf_push_frame(rmdf_ctx *ctx, const float *frame_dev);
 
 /* Copy the velocity field of the latest frame into caller buffers:
  * vxy_dev[H*W*2] = (vx, vy) per anchor; idx_dev[H*W] = candidate index
  * (-1 where a fixed velocity was used); either may be NULL.
- * Errors: RMDF_E_STATE before the first push. */
+ * Paper: v = l / l_z at the maximum of the smoothed autocorrelation on the
+ * l_z = 1 slice (Sec. 2, flow paragraph and eq. 10); the per-pixel velocity
+ * the detector hands on (Sec. 1).  Device-to-device copies on the context
+ * stream; the buffers are the caller's.
+ * Errors: RMDF_E_INVAL (NULL ctx), RMDF_E_STATE before the first push. */
 rmdf_status rmdf_velocity(rmdf_ctx *ctx, float *vxy_dev, int *idx_dev);
 
 /* Copy the prediction-error output of the latest frame into out_dev[H*W].
- * Errors: RMDF_E_STATE before the first push. */
+ * Paper: the whitened output I(n - m') - I^(n - m') (Sec. 2, eq. 1 and 4),
+ * i.e. the foreground plus noise, delayed by m' (Sec. 3: two frames for the
+ * paper's window).  A device-to-device copy on the context stream into the
+ * caller's buffer.
+ * Errors: RMDF_E_INVAL (NULL), RMDF_E_STATE before the first push. */
 rmdf_status rmdf_output(rmdf_ctx *ctx, float *out_dev);
 
 /* Frames pushed so far, and non-finite input samples replaced by zero (the
@@ -179,7 +200,11 @@ rmdf_status rmdf_kernel_time(rmdf_ctx *ctx, int which, double *ms, long long *la
  * FP32 accumulation for the first two, FP32 for the last.
  * Weight blob (host, FP32, row-major [out][in]): W1 128x1152, b1 128,
  * W2 64x128, b2 64, W3 3x64, b3 3 (bytes = 4 * 155,907).  The velocity index
- * of an anchor that used the network is -2. */
+ * of an anchor that used the network is -2.  The upload is enqueued on the
+ * context stream (after the pushes already queued there, which keep the
+ * previous weights) and the call returns once it has completed.
+ * Errors: RMDF_E_INVAL (NULL, wrong size, non-finite weight), RMDF_E_STATE
+ * (context not in learned mode), RMDF_E_DEVICE. */
 rmdf_status rmdf_mlp_set_weights(rmdf_ctx *ctx, const float *blob, size_t bytes);
 /* Features of the latest frame, feat_dev[H*W][1152] BF16 (learned mode or
  * write_features).  Errors: RMDF_E_STATE. */

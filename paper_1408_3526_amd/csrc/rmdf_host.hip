@@ -357,6 +357,8 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
     if (p.write_features)
       return fail(nullptr, RMDF_E_UNSUPPORTED, "write_features needs velocity mode 0");
   }
+  if (!(p.conf_threshold >= 0.f && p.conf_threshold <= 1.f))
+    return fail(nullptr, RMDF_E_INVAL, "conf_threshold must be a finite value in [0, 1]");
   if (p.velocity_mode == RMDF_VEL_FIXED && !(std::isfinite(p.fixed_vx) && std::isfinite(p.fixed_vy)))
     return fail(nullptr, RMDF_E_INVAL, "fixed velocity must be finite");
   if (p.tile_rows < 0) return fail(nullptr, RMDF_E_INVAL, "tile_rows must be >= 0");
@@ -473,6 +475,9 @@ static void timed_end(rmdf_ctx* c, EventPair* ev) {
 rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
   if (!frame) return fail(c, RMDF_E_INVAL, "frame is NULL");
+  // every check precedes the first launch: a refused push leaves the delay
+  // ring, the non-finite counter and the frame count as they were
+  if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
   const size_t HW = (size_t)c->H * c->W;
   float* slot = c->ring + HW * (size_t)(c->t % c->nring);
   EventPair ev{};
@@ -486,7 +491,6 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
 
   rmdf::PixArgs a = rmdf_internal_pixargs(c);
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
-  if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
   const int mode = (c->temporal == RMDF_TEMPORAL_RING) ? 4
                    : (c->vmode == RMDF_VEL_LEARNED) ? 2
                    : (c->vmode == RMDF_VEL_REFINED) ? 3
@@ -641,13 +645,18 @@ rmdf_status rmdf_mlp_set_weights(rmdf_ctx* c, const float* w, size_t bytes) {
   const float* b2 = p; p += 64;
   const float* w3 = p; p += 192;
   const float* b3 = p;
+  // enqueued on the context stream, so the upload is ordered after every push
+  // already queued there (they read the previous weights) and before the next;
+  // the host staging arrays must outlive the copies, hence the synchronisation
   hipError_t e;
-  if ((e = hipMemcpy(c->w1, w1.data(), n1 * 2, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
-  if ((e = hipMemcpy(c->w2, w2.data(), n2 * 2, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
-  if ((e = hipMemcpy(c->b1, b1, 128 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
-  if ((e = hipMemcpy(c->b2, b2, 64 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
-  if ((e = hipMemcpy(c->w3, w3, 192 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
-  if ((e = hipMemcpy(c->b3, b3, 3 * 4, hipMemcpyHostToDevice)) != hipSuccess) return hip_fail(c, e, "upload");
+  auto up = [&](void* dst, const void* src, size_t n) {
+    return hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, c->stream);
+  };
+  if ((e = up(c->w1, w1.data(), n1 * 2)) != hipSuccess || (e = up(c->w2, w2.data(), n2 * 2)) != hipSuccess ||
+      (e = up(c->b1, b1, 128 * 4)) != hipSuccess || (e = up(c->b2, b2, 64 * 4)) != hipSuccess ||
+      (e = up(c->w3, w3, 192 * 4)) != hipSuccess || (e = up(c->b3, b3, 3 * 4)) != hipSuccess)
+    return hip_fail(c, e, "weight upload");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "weight upload");
   c->weights_set = true;
   return RMDF_OK;
 }

@@ -71,7 +71,9 @@ def test_create_rejects_invalid(L, kw):
 
 def test_create_rejects_bad_params(L):
     from paper_1408_3526_amd import binding
-    for field, val in [("Bx", 4), ("By", 9), ("delay_t", 4), ("delay_x", 8), ("alpha", 1.0), ("tile_rows", -1)]:
+    for field, val in [("Bx", 4), ("By", 9), ("delay_t", 4), ("delay_x", 8), ("alpha", 1.0), ("tile_rows", -1),
+                       ("conf_threshold", float("nan")), ("conf_threshold", -0.1), ("conf_threshold", 1.5),
+                       ("conf_threshold", float("inf"))]:
         p = binding.rmdf_params_default()
         setattr(p, field, val)
         st, msg = _create(L, params=p)

@@ -273,3 +273,36 @@ def test_sampled_learned_640x512_against_oracle(orc):
     e = np.concatenate(fe)
     assert np.quantile(e, 0.995) <= 1.0 and np.median(e) <= 0.2, (np.quantile(e, 0.995), np.median(e))
     print("sampled anchors: %d, confident: %d" % (len(pts), int(confident.sum())))
+
+
+def test_refused_push_changes_nothing():
+    """A push refused for missing learned weights (RMDF_E_STATE) is checked
+    before any launch: the frame count, the non-finite counter and the delay
+    ring are as before, so the pushes that follow give the same outputs as a
+    context that never saw the refused frame."""
+    b = _b()
+    sc = scenes.flow_scene(8, H=34, W=37, T=9, n_targets=2, band_width=(6, 9))
+    g = scenes.grid(-4, 4, 0.5)
+    dev = torch.from_numpy(sc.frames).cuda()
+    bad = dev[0].clone()
+    bad[3, 5] = float("nan")
+    bad[10, 1] = float("inf")
+    w = _blob([0.4, -0.3, -20.0])
+    f = b.Filter(34, 37, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9)
+    with pytest.raises(b.RmdfError) as ei:
+        f.push_frame(bad)
+    assert ei.value.status == b.RMDF_E_STATE
+    assert f.frames_pushed() == 0 and f.nonfinite_count() == 0
+    f.set_weights(w)
+    ref = b.Filter(34, 37, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9)
+    ref.set_weights(w)
+    for t in range(9):
+        f.push_frame(dev[t])
+        ref.push_frame(dev[t])
+    out, out_ref = f.output(), ref.output()
+    (vxy, idx), (vxy_r, idx_r) = f.velocity(), ref.velocity()
+    torch.cuda.synchronize()
+    assert f.frames_pushed() == 9 and f.nonfinite_count() == 0
+    assert torch.equal(out, out_ref) and torch.equal(vxy, vxy_r) and torch.equal(idx, idx_r)
+    f.close()
+    ref.close()
