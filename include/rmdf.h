@@ -173,6 +173,20 @@ rmdf_status rmdf_nonfinite_count(rmdf_ctx *ctx, long long *n);
  * Intended for verification.  Errors: RMDF_E_INVAL, RMDF_E_STATE. */
 rmdf_status rmdf_spectrum(rmdf_ctx *ctx, int npix, const int *xs, const int *ys, float *spec_dev);
 
+/* Allocation-free form of rmdf_spectrum, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and errors as
+ * rmdf_spectrum, and the same kernel; the anchor coordinates are staged in a
+ * fixed device array of the library (RMDF_SPECTRUM_NOALLOC_MAX anchors, 512 KB
+ * per GPU, held until the process ends) instead of a buffer the context
+ * allocates, and the call makes no hipMalloc/hipFree.  npix above
+ * RMDF_SPECTRUM_NOALLOC_MAX: RMDF_E_INVAL.  Every call on one GPU shares that
+ * GPU's array: calls that overlap on one GPU (other host threads, or contexts
+ * on other streams) race; calls from one thread do not, since the call
+ * returns only after its stream has finished the copy and the kernel. */
+enum { RMDF_SPECTRUM_NOALLOC_MAX = 65536 };
+rmdf_status rmdf_spectrum_noalloc(rmdf_ctx *ctx, int npix, const int *xs, const int *ys, float *spec_dev);
+
 /* Smoothed autocorrelation R' of the latest frame on the candidate grid,
  * rs_dev[H*W][nvx*nvy] (device, FP32). Errors: RMDF_E_STATE. */
 rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);

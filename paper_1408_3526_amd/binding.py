@@ -41,6 +41,9 @@ class rmdf_params(ctypes.Structure):
                 ("kernel_variant", ctypes.c_int), ("write_features", ctypes.c_int), ("temporal", ctypes.c_int)]
 
 
+# rmdf_spectrum_noalloc: most anchors per call (include/rmdf.h)
+SPECTRUM_NOALLOC_MAX = 65536
+
 # C signatures: name -> (restype, argtypes)
 _VP, _I, _LL, _D, _SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_longlong, ctypes.c_double, ctypes.c_size_t
 _SIGS = {
@@ -53,6 +56,7 @@ _SIGS = {
     "rmdf_frames_pushed": (_I, [_VP, ctypes.POINTER(_LL)]),
     "rmdf_nonfinite_count": (_I, [_VP, ctypes.POINTER(_LL)]),
     "rmdf_spectrum": (_I, [_VP, _I, _VP, _VP, _VP]),
+    "rmdf_spectrum_noalloc": (_I, [_VP, _I, _VP, _VP, _VP]),
     "rmdf_smoothed_r": (_I, [_VP, _VP]),
     "rmdf_set_timing": (_I, [_VP, _I]),
     "rmdf_kernel_time": (_I, [_VP, _I, ctypes.POINTER(_D), ctypes.POINTER(_LL)]),
@@ -241,6 +245,20 @@ class Filter:
         Mx, My, Mz = self.M
         out = torch.empty((n, Mx, My, Mz, 2), dtype=torch.float32, device="cuda")
         _check(lib().rmdf_spectrum(self.ctx, n, xs.ctypes.data, ys.ctypes.data, out.data_ptr()), self.ctx)
+        return torch.view_as_complex(out)
+
+    def spectrum_noalloc(self, xs, ys, out=None):
+        """rmdf_spectrum_noalloc: the same result without any device allocation
+        inside the library (out: a caller buffer [n, Mx, My, Mz, 2] FP32)."""
+        import torch
+        xs = np.ascontiguousarray(xs, np.int32)
+        ys = np.ascontiguousarray(ys, np.int32)
+        n = len(xs)
+        Mx, My, Mz = self.M
+        if out is None:
+            out = torch.empty((n, Mx, My, Mz, 2), dtype=torch.float32, device="cuda")
+        ptr = _dev_ptr(out, torch.float32, n * Mx * My * Mz * 2, "out")
+        _check(lib().rmdf_spectrum_noalloc(self.ctx, n, xs.ctypes.data, ys.ctypes.data, ptr), self.ctx)
         return torch.view_as_complex(out)
 
     def smoothed_r(self):

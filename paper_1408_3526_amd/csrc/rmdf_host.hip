@@ -7,6 +7,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -559,16 +560,27 @@ rmdf_status rmdf_nonfinite_count(rmdf_ctx* c, long long* n) {
   return RMDF_OK;
 }
 
-rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, float* spec) {
-  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+static int spectrum_layout(const rmdf_ctx* c) {
+  return c->temporal == RMDF_TEMPORAL_RING ? 2 : (c->variant == 2 ? 1 : 0);
+}
+
+static rmdf_status spectrum_args(rmdf_ctx* c, int npix, const int* xs, const int* ys, const float* spec) {
   if (npix < 0 || (npix > 0 && (!xs || !ys || !spec))) return fail(c, RMDF_E_INVAL, "bad arguments");
   if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
-  if (npix == 0) return RMDF_OK;
+  for (int i = 0; i < npix; ++i)
+    if (xs[i] < 0 || xs[i] >= c->W || ys[i] < 0 || ys[i] >= c->H) return fail(c, RMDF_E_INVAL, "anchor outside the frame");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, float* spec) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  rmdf_status st = spectrum_args(c, npix, xs, ys, spec);
+  if (st != RMDF_OK || npix == 0) return st;
+  // anchor coordinates staged as (x, y) pairs in a device buffer that grows on demand
   std::vector<int> xy(2 * (size_t)npix);
   for (int i = 0; i < npix; ++i) {
-    if (xs[i] < 0 || xs[i] >= c->W || ys[i] < 0 || ys[i] >= c->H) return fail(c, RMDF_E_INVAL, "anchor outside the frame");
-    xy[2 * i] = xs[i];
-    xy[2 * i + 1] = ys[i];
+    xy[2 * (size_t)i] = xs[i];
+    xy[2 * (size_t)i + 1] = ys[i];
   }
   hipError_t e;
   if (npix > c->xy_cap) {
@@ -578,10 +590,71 @@ rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, f
   if ((e = hipMemcpyAsync(c->xy_scratch, xy.data(), xy.size() * sizeof(int), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return hip_fail(c, e, "anchor upload");
   e = rmdf::launch_spectrum(c->MX, c->MY, c->MZ, c->st, c->W, c->xy_scratch, npix, reinterpret_cast<float2*>(spec),
-                            c->temporal == RMDF_TEMPORAL_RING ? 2 : (c->variant == 2 ? 1 : 0),
-                            (int)((c->t - 1) & 0x3fffffff), c->stream);
+                            spectrum_layout(c), (int)((c->t - 1) & 0x3fffffff), c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "spectrum launch");
   // the host array must outlive the copy
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "sync");
+  return RMDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of rmdf_spectrum.  The anchor coordinates go to a
+// file-scope device array instead of a buffer the context allocates: xs in
+// [0, MAX), ys in [MAX, 2 MAX).  Host code never passes the array's name to a
+// kernel or a copy (on the host it is only a stand-in symbol): its device
+// address is looked up once per device with hipGetSymbolAddress, with that
+// device current, and that address is used everywhere.
+static __device__ __align__(256) int scratch[2 * RMDF_SPECTRUM_NOALLOC_MAX];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+int* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on `device` (looked up on the first call for that
+// device, with the device made current for the lookup).
+static hipError_t noalloc_scratch(int device, int** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr && g_scratch_err[device] == hipSuccess) {
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != device) e = hipSetDevice(device);
+    void* p = nullptr;
+    if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur >= 0 && cur != device) {
+      const hipError_t e2 = hipSetDevice(cur);
+      if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess && p == nullptr) e = hipErrorInvalidSymbol;
+    if (e == hipSuccess) g_scratch_ptr[device] = static_cast<int*>(p);
+    else g_scratch_err[device] = e;
+  }
+  *out = g_scratch_ptr[device];
+  return g_scratch_ptr[device] ? hipSuccess : g_scratch_err[device];
+}
+
+rmdf_status rmdf_spectrum_noalloc(rmdf_ctx* c, int npix, const int* xs, const int* ys, float* spec) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (npix > RMDF_SPECTRUM_NOALLOC_MAX)
+    return fail(c, RMDF_E_INVAL, "too many anchors for the allocation-free call (at most RMDF_SPECTRUM_NOALLOC_MAX)");
+  rmdf_status st = spectrum_args(c, npix, xs, ys, spec);
+  if (st != RMDF_OK || npix == 0) return st;
+  int* dev = nullptr;
+  hipError_t e = noalloc_scratch(c->device, &dev);
+  if (e != hipSuccess) return hip_fail(c, e, "scratch address");
+  int* dxs = dev;
+  int* dys = dev + RMDF_SPECTRUM_NOALLOC_MAX;
+  if ((e = hipMemcpyAsync(dxs, xs, sizeof(int) * npix, hipMemcpyHostToDevice, c->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(dys, ys, sizeof(int) * npix, hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return hip_fail(c, e, "anchor upload");
+  e = rmdf::launch_spectrum_at(c->MX, c->MY, c->MZ, c->st, c->W, dxs, dys, 1, npix, reinterpret_cast<float2*>(spec),
+                               spectrum_layout(c), (int)((c->t - 1) & 0x3fffffff), c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "spectrum launch");
+  // the caller's host arrays must outlive the copies
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "sync");
   return RMDF_OK;

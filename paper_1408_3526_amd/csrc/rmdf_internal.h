@@ -16,3 +16,10 @@ void rmdf_internal_shape(const rmdf_ctx* c, int* mx, int* my, int* mz, int* vari
 // Count one frame pushed by someone else (the batched step).
 void rmdf_internal_advance(rmdf_ctx* c);
 void rmdf_internal_set_create_error(const std::string& m);
+
+namespace rmdf {
+// Local spectrum at anchors (xs[i * cstride], ys[i * cstride]) (device arrays);
+// launch_spectrum (rmdf_kernels.h) is the interleaved (x, y) form.
+hipError_t launch_spectrum_at(int mx, int my, int mz, const float2* st, int W, const int* xs, const int* ys,
+                              int cstride, int npix, float2* out, int layout, int newest, hipStream_t s);
+}  // namespace rmdf

@@ -57,15 +57,15 @@ __global__ void __launch_bounds__(256) k_pixel(PixArgs a) {
 // spectra [slot][plane][ky] (newest frame in slot newest mod Mz), from which
 // X_kz = (1/Mz) sum_m w^(kz m) S2(t - m) is formed here.
 template <int MX, int MY, int MZ, int LAYOUT>
-__global__ void k_spectrum(const float2* __restrict__ st, int W, const int* __restrict__ xy, int npix,
-                           float2* __restrict__ out, int newest) {
+__global__ void k_spectrum(const float2* __restrict__ st, int W, const int* __restrict__ xs,
+                           const int* __restrict__ ys, int cstride, int npix, float2* __restrict__ out, int newest) {
   using SH = Shape<MX, MY, MZ>;
   constexpr int N = MX * MY * MZ;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= npix * N) return;
   const int ip = gid / N, b = gid % N;
   int kx = b / (MY * MZ), kyy = (b / MZ) % MY, kz = b % MZ;
-  const size_t pix = (size_t)xy[2 * ip + 1] * W + xy[2 * ip];
+  const size_t pix = (size_t)ys[(size_t)ip * cstride] * W + xs[(size_t)ip * cstride];
   const float2* S = st + pix * SH::NCOL * MZ;
   auto X = [&](int p, int ky, int k) -> float2 {
     if (LAYOUT == 2) {
@@ -118,11 +118,11 @@ static hipError_t launch_row_t(const float* f, float2* rs, const float2* twx, in
 }
 
 template <int MX, int MY, int MZ, int IL>
-static hipError_t launch_spec_t(const float2* st, int W, const int* xy, int npix, float2* out, int newest,
-                                hipStream_t s) {
+static hipError_t launch_spec_t(const float2* st, int W, const int* xs, const int* ys, int cstride, int npix,
+                                float2* out, int newest, hipStream_t s) {
   const int n = npix * MX * MY * MZ;
-  hipLaunchKernelGGL((k_spectrum<MX, MY, MZ, IL>), dim3((n + 255) / 256), dim3(256), 0, s, st, W, xy, npix, out,
-                     newest);
+  hipLaunchKernelGGL((k_spectrum<MX, MY, MZ, IL>), dim3((n + 255) / 256), dim3(256), 0, s, st, W, xs, ys, cstride,
+                     npix, out, newest);
   return hipGetLastError();
 }
 
@@ -164,16 +164,24 @@ hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int
   return hipErrorInvalidValue;
 }
 
+// Anchor i is (xs[i * cstride], ys[i * cstride]) (device arrays).
+hipError_t launch_spectrum_at(int mx, int my, int mz, const float2* st, int W, const int* xs, const int* ys,
+                              int cstride, int npix, float2* out, int layout, int newest, hipStream_t s) {
+  if (npix > (1 << 30) / (mx * my * mz)) return hipErrorInvalidValue;   // thread count must fit an int
+  if (mx == 8 && my == 8 && mz == 4) return launch_spec_t<8, 8, 4, 0>(st, W, xs, ys, cstride, npix, out, newest, s);
+  if (mx == 16 && my == 16 && mz == 8) {
+    if (layout == 2) return launch_spec_t<16, 16, 8, 2>(st, W, xs, ys, cstride, npix, out, newest, s);
+    return layout == 1 ? launch_spec_t<16, 16, 8, 1>(st, W, xs, ys, cstride, npix, out, newest, s)
+                       : launch_spec_t<16, 16, 8, 0>(st, W, xs, ys, cstride, npix, out, newest, s);
+  }
+  if (mx == 9 && my == 9 && mz == 5) return launch_spec_t<9, 9, 5, 0>(st, W, xs, ys, cstride, npix, out, newest, s);
+  return hipErrorInvalidValue;
+}
+
+// Anchors as (x, y) pairs: xy[2 i], xy[2 i + 1].
 hipError_t launch_spectrum(int mx, int my, int mz, const float2* st, int W, const int* xy, int npix, float2* out,
                            int layout, int newest, hipStream_t s) {
-  if (mx == 8 && my == 8 && mz == 4) return launch_spec_t<8, 8, 4, 0>(st, W, xy, npix, out, newest, s);
-  if (mx == 16 && my == 16 && mz == 8) {
-    if (layout == 2) return launch_spec_t<16, 16, 8, 2>(st, W, xy, npix, out, newest, s);
-    return layout == 1 ? launch_spec_t<16, 16, 8, 1>(st, W, xy, npix, out, newest, s)
-                       : launch_spec_t<16, 16, 8, 0>(st, W, xy, npix, out, newest, s);
-  }
-  if (mx == 9 && my == 9 && mz == 5) return launch_spec_t<9, 9, 5, 0>(st, W, xy, npix, out, newest, s);
-  return hipErrorInvalidValue;
+  return launch_spectrum_at(mx, my, mz, st, W, xy, xy + 1, 2, npix, out, layout, newest, s);
 }
 
 

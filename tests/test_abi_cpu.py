@@ -89,7 +89,15 @@ def test_null_context_calls(L):
     assert L.rmdf_push_frame(None, None) == -1
     assert L.rmdf_output(None, None) == -1
     assert L.rmdf_velocity(None, None, None) == -1
+    assert L.rmdf_spectrum_noalloc(None, 0, None, None, None) == -1
     assert L.rmdf_destroy(None) == 0
+
+
+def test_noalloc_limit_matches_header():
+    from paper_1408_3526_amd import binding
+    txt = open(os.path.join(ROOT, "include", "rmdf.h")).read()
+    m = re.search(r"RMDF_SPECTRUM_NOALLOC_MAX\s*=\s*(\d+)", txt)
+    assert m and int(m.group(1)) == binding.SPECTRUM_NOALLOC_MAX
 
 
 @pytest.mark.skipif(os.environ.get("HIP_VISIBLE_DEVICES") is None and os.path.exists("/dev/kfd"),
