@@ -57,26 +57,67 @@ def test_transpose():
     assert torch.equal(out, x.t().contiguous())
 
 
-def test_training_gradients_match_reference():
+def _trainer_with(params, n):
+    """A Trainer whose FP32 master weights (and their BF16 copies) are params."""
     from paper_1408_3526_amd import learned
-    rng = np.random.default_rng(3)
-    n = 512
-    X = mlp.bf16_round(rng.normal(size=(n, mlp.N_IN)))
-    lab = rng.uniform(-3, 3, size=(n, 2)).astype(np.float32)
+    b = _b()
     tr = learned.Trainer(seed=1, batch=n)
-    params = [tr.p[k].cpu().numpy().astype(np.float64) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]
-    # make the bias terms and the confidence head non-trivial
-    for k, i in (("b1", 1), ("b2", 3), ("b3", 5)):
-        params[i] = rng.normal(scale=0.1, size=params[i].shape)
-        tr.p[k].copy_(torch.from_numpy(params[i].astype(np.float32)))
+    for k, a in zip(("W1", "b1", "W2", "b2", "W3", "b3"), params):
+        tr.p[k].copy_(torch.from_numpy(np.asarray(a, np.float32)))
+    b.mlp_to_bf16(tr.p["W1"], tr.bf["W1"])
+    b.mlp_to_bf16(tr.p["W2"], tr.bf["W2"])
+    return tr
+
+
+@pytest.mark.parametrize("n,seed", [(512, 3), (1000, 4)])
+def test_training_gradients_within_elementwise_bounds(n, seed):
+    """Every element of dW1, db1, dW2, db2, dW3, db3 and the loss of one
+    training batch lies inside the interval oracle/mlp.grads_iv derives around
+    the FP64 reference: FP32 accumulation error in any order, and one BF16 ulp
+    (or either ReLU mask) wherever the rounding of H1, H2, dH2 or dH1 can go
+    either way.  Labels sit near the network's output so that both
+    confidence targets occur, each clear of the threshold.""" 
+    from mlp_cases import random_params
+    rng = np.random.default_rng(seed)
+    X = mlp.bf16_round(rng.normal(size=(n, mlp.N_IN)))
+    params = random_params(rng)
+    O = mlp.forward(X, params)[-1]
+    # half the samples within 0.2 of the output in both components (target
+    # 1), the others 0.3-0.6 away in one (target 0): both targets, each at
+    # least 0.05 from the 0.25 threshold
+    near = rng.uniform(-0.2, 0.2, size=(n, 2))
+    far = near.copy()
+    far[np.arange(n), rng.integers(0, 2, n)] = rng.choice([-1, 1], n) * rng.uniform(0.3, 0.6, n)
+    lab = np.float32(O[:, :2] + np.where(rng.uniform(size=(n, 1)) < 0.5, near, far))
+    tr = _trainer_with(params, n)
     loss = tr.grads(_bf(X), torch.from_numpy(lab).cuda())
     torch.cuda.synchronize()
-    rl, rg = mlp.loss_and_grads(X, lab.astype(np.float64), params, wv=tr.wv, half_step=tr.half_step, bf16=True)
-    assert abs(float(loss.item()) - rl) <= 1e-3 * abs(rl)
+    (lm, lr), g = mlp.grads_iv(X, lab, params, wv=tr.wv, half_step=tr.half_step)
+    assert mlp.within(float(loss.item()), lm, lr), (float(loss.item()), lm, lr)
+    for k, (mid, rad) in g.items():
+        got = tr.g[k].cpu().numpy().astype(np.float64)
+        ok = mlp.within(got, mid, rad)
+        excess = (np.abs(got - mid) - rad)[~ok]
+        assert ok.all(), (k, int((~ok).sum()), float(excess.max()) if excess.size else 0.0)
+        print("%s: %d elements, median bound %.2e x max|G|, %.1f%% of bounds above 1e-3 x max|G|"
+              % (k, got.size, np.median(rad) / np.abs(mid).max(), 100 * np.mean(rad > 1e-3 * np.abs(mid).max())))
+
+
+def test_training_gradients_exact_on_integer_data():
+    """Integer inputs and weights whose every FP32 sum is exactly
+    representable (checked): the GPU's loss gradients equal the FP64
+    reference bit for bit, element by element."""
+    from mlp_cases import exactness_premise, integer_case
+    X, lab, params = integer_case()
+    n = X.shape[0]
+    assert exactness_premise(X, lab, params, n) < 1.0
+    tr = _trainer_with(params, n)
+    tr.grads(_bf(X), torch.from_numpy(np.asarray(lab, np.float32)).cuda())
+    torch.cuda.synchronize()
+    _, rg = mlp.loss_and_grads(X, lab, params, wv=tr.wv, half_step=tr.half_step, bf16=True)
     for k, G in zip(("W1", "b1", "W2", "b2", "W3", "b3"), rg):
-        g = tr.g[k].cpu().numpy().astype(np.float64)
-        rel = np.linalg.norm(g - G) / max(np.linalg.norm(G), 1e-30)
-        assert rel <= 1e-2, (k, rel)
+        got = tr.g[k].cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, G), (k, int(np.sum(got != G)))
 
 
 def test_adam_step():
@@ -97,7 +138,30 @@ def test_adam_step():
     assert torch.equal(pb, tp.to(torch.bfloat16))
 
 
+def _check_features(orc, cfg, frames, pts, F, S_gpu):
+    """Element-wise: the GPU's local spectrum at each anchor within
+    TAU_S * max|S| of the oracle's (direct window DFT), and every one of its
+    1152 BF16 features inside mlp.features_iv's bound around the oracle's.
+    Returns the oracle's features and bounds."""
+    xs, rads = [], []
+    for i, (x, y) in enumerate(pts):
+        S = orc.pixel_series(cfg, frames, x, y)["S"][-1]
+        scale = np.abs(S).max()
+        assert np.abs(S_gpu[i] - S).max() <= mlp.TAU_S * scale, (x, y, np.abs(S_gpu[i] - S).max() / scale)
+        _, P = orc.flow_R(cfg, S, want_P=True)
+        xr, rad = mlp.features_iv(P, scale)
+        err = np.abs(F[i].astype(np.float64) - xr)
+        assert np.all(err <= rad), (x, y, int(np.sum(err > rad)), float(np.max(err / rad)))
+        xs.append(xr)
+        rads.append(rad)
+    return np.array(xs), np.array(rads)
+
+
 def test_features_match_oracle(orc):
+    """Search mode with feature output: at sampled anchors (corners, borders,
+    interior) every feature is within its derived bound of the oracle's
+    log power spectrum, and the spectrum itself within TAU_S of the largest
+    bin."""
     b = _b()
     sc = scenes.flow_scene(5, H=36, W=40, T=10, n_targets=2, band_width=(6, 9))
     g = scenes.grid(-4, 4, 0.5)
@@ -105,19 +169,50 @@ def test_features_match_oracle(orc):
     dev = torch.from_numpy(sc.frames).cuda()
     for t in range(10):
         f.push_frame(dev[t])
+    pts = [(39, 35), (20, 20), (15, 30), (0, 0), (5, 33), (39, 0), (0, 35)]
     F = f.features().float().cpu().numpy()
+    F = np.array([F[y, x] for (x, y) in pts])
+    S_gpu = f.spectrum([p[0] for p in pts], [p[1] for p in pts]).cpu().numpy()
     torch.cuda.synchronize()
     f.close()
     cfg = orc.Cfg(H=36, W=40, Mx=16, My=16, Mz=8, gx=g, gy=g)
-    pts = [(39, 35), (20, 20), (15, 30), (0, 0), (5, 33)]
-    errs = []
-    for (x, y) in pts:
-        p = orc.pixel_series(cfg, sc.frames, x, y)
-        _, P = orc.flow_R(cfg, p["S"][-1], want_P=True)
-        ref = mlp.features_from_P(P)
-        errs.append(np.abs(F[y, x] - ref) / (0.05 + 0.01 * np.abs(ref)))
-    e = np.concatenate(errs)
-    assert np.quantile(e, 0.995) <= 1.0 and np.median(e) <= 0.2, (np.quantile(e, 0.995), np.median(e))
+    _check_features(orc, cfg, sc.frames, pts, F, S_gpu)
+
+
+def test_inference_kernels_within_bounds():
+    """The learned mode's network kernels (the two MFMA GEMM layers and the
+    head, launched as a push launches them) on realistic inputs: every
+    output (vx, vy, confidence) lies inside the interval oracle/mlp.forward_iv
+    derives around the FP64 forward pass of the shipped network."""
+    import os
+
+    from paper_1408_3526_amd import learned
+    if not os.path.exists(learned.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights shipped")
+    b = _b()
+    w = np.load(learned.DEFAULT_WEIGHTS)
+    params = mlp.unpack(w)
+    rng = np.random.default_rng(21)
+    n = 3000
+    # log-spectrum-like inputs: a smooth decay over the bins plus noise
+    X = mlp.bf16_round(rng.normal(size=(n, mlp.N_IN)) * 1.5 - np.linspace(0, 6, mlp.N_IN)[None, :] + 3.0)
+    W1b = _bf(params[0])
+    W2b = _bf(params[2])
+    h1 = torch.empty(n, mlp.N_H1, dtype=torch.bfloat16, device="cuda")
+    h2 = torch.empty(n, mlp.N_H2, dtype=torch.bfloat16, device="cuda")
+    vc = torch.empty(n, 3, device="cuda")
+    f32 = lambda a: torch.from_numpy(np.asarray(a, np.float32)).cuda()  # noqa: E731
+    b.mlp_gemm_nt(_bf(X), W1b, bias=f32(params[1]), epi=1, out_bf16=h1)
+    b.mlp_gemm_nt(h1, W2b, bias=f32(params[3]), epi=1, out_bf16=h2)
+    b.mlp_infer_head(h2, f32(params[4]), f32(params[5]), vc)
+    got = vc.cpu().numpy().astype(np.float64)
+    torch.cuda.synchronize()
+    fw = mlp.forward_iv(X, 0, params)
+    Om, Or = fw["O"]
+    assert mlp.within(got[:, :2], Om[:, :2], Or[:, :2]).all()
+    clo, chi = mlp.sigmoid_iv(Om[:, 2], Or[:, 2])
+    assert np.all((got[:, 2] >= clo) & (got[:, 2] <= chi))
+    print("output bound: median %.2e, max %.2e (px/frame)" % (np.median(Or[:, :2]), Or[:, :2].max()))
 
 
 def _blob(b3):
@@ -206,12 +301,15 @@ def test_trained_network_against_search():
 def test_sampled_learned_640x512_against_oracle(orc):
     """Learned mode on 640x512 frames with the shipped network, the
     configuration the benchmark times (16x16x8, 17x17 grid at 0.5 px/frame,
-    confidence threshold 0.9).  At sampled anchors of the last frame:
-    the features equal the oracle's log power spectrum; the network's outputs
-    equal the FP64 forward pass on the GPU's own BF16 features; an anchor
-    takes the network's velocity (index -2) exactly where its confidence
-    reaches 0.9 and otherwise the instantaneous search's grid maximum; the
-    output equals the oracle's filter (eq. 4 with eq. 8) at the velocity taken."""
+    confidence threshold 0.9).  At sampled anchors of the last frame, element
+    by element: the spectrum and the 1152 features within their derived
+    bounds of the oracle's; the network's outputs inside the interval that
+    those feature bounds give through the FP64 forward pass (mlp.forward_iv);
+    the anchor takes the network's velocity (index -2) exactly where its
+    confidence reaches 0.9 (and where the oracle's confidence interval lies on
+    one side of 0.9, that side), otherwise the instantaneous search's grid
+    maximum; the output equals the oracle's filter (eq. 4 with eq. 8) at the
+    velocity taken."""
     import os
 
     from paper_1408_3526_amd import learned
@@ -237,26 +335,29 @@ def test_sampled_learned_640x512_against_oracle(orc):
     vxy, idx = f.velocity()
     vxy, idx = vxy[ys, xs].cpu().numpy(), idx[ys, xs].cpu().numpy()
     out = f.output()[ys, xs].cpu().numpy()
+    S_gpu = f.spectrum([p[0] for p in pts], [p[1] for p in pts]).cpu().numpy()
     torch.cuda.synchronize()
     f.close()
 
-    # network: FP64 forward pass on the same BF16 inputs
-    O = mlp.forward(F, mlp.unpack(w))[-1]
-    conf = 1.0 / (1.0 + np.exp(-O[:, 2]))
-    assert np.abs(vc[:, :2] - O[:, :2]).max() <= 0.02 + 0.01 * np.abs(O[:, :2]).max()
-    assert np.abs(vc[:, 2] - conf).max() <= 0.01
+    cfg = orc.Cfg(H=H, W=W, Mx=16, My=16, Mz=8, gx=g, gy=g, alpha=0.0)
+    Xr, Xrad = _check_features(orc, cfg, sc.frames, pts, F, S_gpu)
+    # network outputs inside the interval propagated from the feature bounds
+    params = mlp.unpack(w)
+    fw = mlp.forward_iv(Xr, Xrad, params)
+    Om, Or = fw["O"]
+    assert mlp.within(vc[:, :2], Om[:, :2], Or[:, :2]).all()
+    clo, chi = mlp.sigmoid_iv(Om[:, 2], Or[:, 2])
+    assert np.all((vc[:, 2] >= clo) & (vc[:, 2] <= chi))
     confident = vc[:, 2] >= 0.9
     assert np.array_equal(idx == -2, confident)
     assert np.array_equal(vxy[confident], vc[confident, :2])
+    assert not np.any(confident & (chi < 0.9)) and np.all(confident | (clo < 0.9))
 
-    cfg = orc.Cfg(H=H, W=W, Mx=16, My=16, Mz=8, gx=g, gy=g, alpha=0.0)
     rms = float(np.sqrt(np.mean(sc.frames[T - 1].astype(np.float64) ** 2)))
-    fe = []
     for i, (x, y) in enumerate(pts):
         p = orc.pixel_series(cfg, sc.frames, x, y)
         S = p["S"][-1]
         R, P = orc.flow_R(cfg, S, want_P=True)
-        fe.append(np.abs(F[i] - mlp.features_from_P(P)) / (0.05 + 0.01 * np.abs(mlp.features_from_P(P))))
         if not confident[i]:
             # fallback: first maximum of the instantaneous R (ties: any near-maximal pick)
             scale = max(np.abs(R).max(), 1e-3 * P.sum(), 1e-30)
@@ -270,9 +371,8 @@ def test_sampled_learned_640x512_against_oracle(orc):
         ts, xd, yd = T - 1 - cfg.dt, x - cfg.dx, y - cfg.dy
         delayed = float(sc.frames[ts, yd, xd]) if (xd >= 0 and yd >= 0) else 0.0
         assert abs(out[i] - (delayed - ihat)) <= 1e-3 * rms, (x, y, out[i], delayed - ihat)
-    e = np.concatenate(fe)
-    assert np.quantile(e, 0.995) <= 1.0 and np.median(e) <= 0.2, (np.quantile(e, 0.995), np.median(e))
-    print("sampled anchors: %d, confident: %d" % (len(pts), int(confident.sum())))
+    print("sampled anchors: %d, confident: %d, output bound median %.3g px/frame"
+          % (len(pts), int(confident.sum()), float(np.median(Or[:, :2]))))
 
 
 def test_refused_push_changes_nothing():
