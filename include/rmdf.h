@@ -94,12 +94,20 @@ typedef struct {
                                last Mz 2-D spectra per pixel and the Mz-point
                                temporal DFT taken directly each frame (the same
                                spectrum; the non-recursive comparison point of
-                               Sec. 5 applied to time only).  The ring needs the
-                               16x16x8 wave-per-anchor kernel and the search or
-                               fixed velocity mode; single contexts only.     */
+                               Sec. 5 applied to time only);
+                               RMDF_TEMPORAL_DIRECT (2): no recursion on any
+                               axis, the non-recursive local spectrum of
+                               Sec. 5: every row-spectrum bin is the direct
+                               Kx-term DFT sum of its window, every 2-D bin the
+                               direct Ky-term sum over the window's row spectra,
+                               and the temporal part as in the ring (the same
+                               spectrum in exact arithmetic).  The ring and the
+                               direct form need the 16x16x8 wave-per-anchor
+                               kernel and the search or fixed velocity mode;
+                               single contexts only.                          */
 } rmdf_params;
 
-enum { RMDF_TEMPORAL_OBSERVER = 0, RMDF_TEMPORAL_RING = 1 };
+enum { RMDF_TEMPORAL_OBSERVER = 0, RMDF_TEMPORAL_RING = 1, RMDF_TEMPORAL_DIRECT = 2 };
 
 /* Fill *p with the defaults above (the -1 / negative markers). */
 void rmdf_params_default(rmdf_params *p);
@@ -110,7 +118,8 @@ void rmdf_params_default(rmdf_params *p);
  * hip_stream: the hipStream_t every call of this context enqueues on; NULL
  * means the device's default (null) stream.
  * Allocates all device state (observer state H*W*Kx*Ky*Kt/2 complex FP32, or
- * the ring of Kt 2-D spectra of the same size with RMDF_TEMPORAL_RING,
+ * the ring of Kt 2-D spectra of the same size with RMDF_TEMPORAL_RING or
+ * RMDF_TEMPORAL_DIRECT,
  * smoothed autocorrelation H*W*nvx*nvy FP32, row spectra, a (m'_t+1)-frame
  * delay ring, tables) and zeroes it.
  * Compiled window shapes: 8x8x4, 16x16x8, 9x9x5 (others: RMDF_E_UNSUPPORTED).
@@ -283,6 +292,16 @@ rmdf_status rmdf_coeff_lattice(const rmdf_ctx *ctx, int *lattice_q);
  * enqueued on `stream` (NULL: the default stream) and allocates nothing. */
 rmdf_status rmdf_cfar(const float *x_dev, int H, int W, int guard, int train, float k,
                       unsigned char *det_dev, float *level_dev, void *stream);
+
+/* HBM streaming probe (measurement utility, not part of the filter): one
+ * grid-stride pass of 16-byte accesses over `bytes` of device memory on
+ * `stream` (NULL: default stream), n_blocks workgroups of 256 threads.
+ * kind 0 read src (dst receives n_blocks partial sums, so dst must hold
+ * n_blocks floats), 1 write dst, 2 copy src to dst.  nt != 0: non-temporal
+ * loads and stores.  bytes a positive multiple of 16, pointers 16-byte
+ * aligned; otherwise RMDF_E_INVAL.  Timing is the caller's (events around the
+ * call).  Gives the practical ceiling beside the data-sheet HBM peak. */
+rmdf_status rmdf_hbm_probe(int kind, const void *src, void *dst, size_t bytes, int n_blocks, int nt, void *stream);
 
 /* Bytes of device memory the context holds. */
 rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);

@@ -20,7 +20,7 @@ _LIB = None
 
 RMDF_OK, RMDF_E_INVAL, RMDF_E_NOMEM, RMDF_E_DEVICE, RMDF_E_STATE, RMDF_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 VEL_SEARCH, VEL_LEARNED, VEL_FIXED, VEL_REFINED = 0, 1, 2, 3
-TEMPORAL_OBSERVER, TEMPORAL_RING = 0, 1
+TEMPORAL_OBSERVER, TEMPORAL_RING, TEMPORAL_DIRECT = 0, 1, 2
 
 _STATUS = {0: "RMDF_OK", -1: "RMDF_E_INVAL", -2: "RMDF_E_NOMEM", -3: "RMDF_E_DEVICE",
            -4: "RMDF_E_STATE", -5: "RMDF_E_UNSUPPORTED"}
@@ -65,6 +65,7 @@ _SIGS = {
     "rmdf_coeff_lattice": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_tile_rows": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_cfar": (_I, [_VP, _I, _I, _I, _I, ctypes.c_float, _VP, _VP, _VP]),
+    "rmdf_hbm_probe": (_I, [_I, _VP, _VP, _SZ, _I, _I, _VP]),
     "rmdf_destroy": (_I, [_VP]),
     "rmdf_last_error": (ctypes.c_char_p, [_VP]),
     "rmdf_mlp_set_weights": (_I, [_VP, _VP, _SZ]),
@@ -532,3 +533,11 @@ def cfar(x, guard: int, train: int, k: float, want_level: bool = False):
     _check(lib().rmdf_cfar(xp, int(H), int(W), int(guard), int(train), float(k), det.data_ptr(), _p(lev),
                            ctypes.c_void_p(_stream_handle())))
     return (det, lev) if want_level else det
+
+
+def hbm_probe(kind: int, src, dst, nbytes: int, n_blocks: int, nt: bool = False):
+    """One pass of the HBM streaming probe (rmdf_hbm_probe) on torch's current
+    stream: kind 0 read src (dst: n_blocks FP32 partial sums), 1 write dst,
+    2 copy src to dst."""
+    _check(lib().rmdf_hbm_probe(int(kind), None if src is None else src.data_ptr(), dst.data_ptr(), int(nbytes),
+                                int(n_blocks), int(bool(nt)), _stream_handle()))

@@ -37,7 +37,9 @@ struct RowShape {
 // read as 0; when `nonfinite` is given, those of the chunk's own columns are
 // counted; when `copy_to` is given, the chunk's own columns are stored there
 // (non-finite ones as 0): the frame's copy into the delay ring.
-template <int MX>
+// DIRECT: every output is the direct Mx-term DFT sum of its window (no comb,
+// no resonator): the non-recursive form of the same row spectrum.
+template <int MX, bool DIRECT = false>
 static __device__ void row_chunk(const float* __restrict__ f, float2* __restrict__ rs, const float2* __restrict__ twx,
                           int H, int W, int y, int x0, char* smem, unsigned long long* nonfinite,
                           float* __restrict__ copy_to = nullptr) {
@@ -68,7 +70,32 @@ static __device__ void row_chunk(const float* __restrict__ f, float2* __restrict
   }
   __syncthreads();
   const float inv = rsqrtf((float)MX);
-  if (threadIdx.x < NP * NSEG) {
+  if (DIRECT && threadIdx.x < NP * NSEG) {
+    // A(kx; x) = sum_m w^(kx m) I(x - m), m = 0 .. Mx - 1, for each column
+    const int p = threadIdx.x / NSEG, sg = threadIdx.x % NSEG;
+    const int xs = sg * RSEG;
+    for (int i = 0; i < RSEG; ++i) {
+      const int xi = xs + i;
+      if (p == 0) {
+        float a0 = 0.f, ah = 0.f;
+        for (int m = 0; m < MX; ++m) {
+          const float v = s_in[MX + xi - m];
+          a0 += v;
+          ah += (m & 1) ? -v : v;
+        }
+        s_out[xi] = EVEN ? make_float2(a0 * inv, ah * inv) : make_float2(a0 * inv, 0.f);
+      } else {
+        float2 acc = make_float2(0.f, 0.f);
+        for (int m = 0; m < MX; ++m) {
+          const float v = s_in[MX + xi - m];
+          const float2 w = s_tw[(p * m) % MX];
+          acc.x += w.x * v;
+          acc.y += w.y * v;
+        }
+        s_out[p * RCX + xi] = cscale(acc, inv);
+      }
+    }
+  } else if (threadIdx.x < NP * NSEG) {
     const int p = threadIdx.x / NSEG, sg = threadIdx.x % NSEG;
     const int xs = sg * RSEG;             // segment start relative to x0
     if (p == 0) {

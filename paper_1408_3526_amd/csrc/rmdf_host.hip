@@ -54,7 +54,7 @@ struct rmdf_ctx {
   float *gx = nullptr, *gy = nullptr, *tabB = nullptr, *tabC = nullptr;
   int variant = 0;                 // resolved kernel variant (1 generic, 2 wave-per-anchor)
   int write_features = 0;          // plain search that also writes the learned-model input
-  int temporal = 0;                // RMDF_TEMPORAL_*: observer state or ring of 2-D spectra
+  int temporal = 0;                // RMDF_TEMPORAL_*: observer state, or ring of 2-D spectra (ring, direct)
   // learned velocity surrogate (16x16x8): features, hidden activations, outputs, weights
   unsigned short* feat = nullptr;  // [HW][1152] BF16
   int* fidx = nullptr;             // [HW] search index (fallback)
@@ -367,14 +367,16 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   const bool w16 = rmdf::pixel16_eligible(Kx, Ky, Kt, nvx, nvy);
   if (p.kernel_variant == 2 && !w16)
     return fail(nullptr, RMDF_E_UNSUPPORTED, "kernel_variant 2 needs a 16x16x8 window and at most 21 candidates per axis");
-  if (p.temporal != RMDF_TEMPORAL_OBSERVER && p.temporal != RMDF_TEMPORAL_RING)
+  if (p.temporal != RMDF_TEMPORAL_OBSERVER && p.temporal != RMDF_TEMPORAL_RING && p.temporal != RMDF_TEMPORAL_DIRECT)
     return fail(nullptr, RMDF_E_INVAL, "unknown temporal mode");
-  if (p.temporal == RMDF_TEMPORAL_RING) {
+  if (p.temporal != RMDF_TEMPORAL_OBSERVER) {
     if (!w16 || p.kernel_variant == 1)
       return fail(nullptr, RMDF_E_UNSUPPORTED,
-                  "the temporal ring needs the 16x16x8 window, kernel variant 2 and at most 21 candidates per axis");
+                  "the temporal ring and the direct spectrum need the 16x16x8 window, kernel variant 2 and at most 21 "
+                  "candidates per axis");
     if ((p.velocity_mode != RMDF_VEL_SEARCH && p.velocity_mode != RMDF_VEL_FIXED) || p.write_features)
-      return fail(nullptr, RMDF_E_UNSUPPORTED, "the temporal ring supports the search and fixed velocity modes");
+      return fail(nullptr, RMDF_E_UNSUPPORTED,
+                  "the temporal ring and the direct spectrum support the search and fixed velocity modes");
   }
   const bool needs16 = (p.velocity_mode == RMDF_VEL_LEARNED) || p.write_features;
   if (needs16 && (!w16 || p.kernel_variant == 1))
@@ -486,13 +488,15 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   // row sliding DFT straight from the caller's frame; the same kernel stores
   // the frame (non-finite samples zeroed and counted) into the delay ring
   timed_begin(c, 1, &ev);
-  e = rmdf::launch_row(c->MX, frame, c->rs, c->twx, c->H, c->W, slot, c->nonfinite, c->stream);
+  e = rmdf::launch_row(c->MX, frame, c->rs, c->twx, c->H, c->W, slot, c->nonfinite, c->stream,
+                       c->temporal == RMDF_TEMPORAL_DIRECT);
   timed_end(c, &ev);
   if (e != hipSuccess) return hip_fail(c, e, "row kernel launch");
 
   rmdf::PixArgs a = rmdf_internal_pixargs(c);
   a.ring_delayed = (c->t >= c->dt) ? c->ring + HW * (size_t)((c->t - c->dt) % c->nring) : nullptr;
-  const int mode = (c->temporal == RMDF_TEMPORAL_RING) ? 4
+  const int mode = (c->temporal == RMDF_TEMPORAL_DIRECT) ? 5
+                   : (c->temporal == RMDF_TEMPORAL_RING) ? 4
                    : (c->vmode == RMDF_VEL_LEARNED) ? 2
                    : (c->vmode == RMDF_VEL_REFINED) ? 3
                    : (c->write_features ? 1 : 0);
@@ -561,7 +565,7 @@ rmdf_status rmdf_nonfinite_count(rmdf_ctx* c, long long* n) {
 }
 
 static int spectrum_layout(const rmdf_ctx* c) {
-  return c->temporal == RMDF_TEMPORAL_RING ? 2 : (c->variant == 2 ? 1 : 0);
+  return c->temporal != RMDF_TEMPORAL_OBSERVER ? 2 : (c->variant == 2 ? 1 : 0);
 }
 
 static rmdf_status spectrum_args(rmdf_ctx* c, int npix, const int* xs, const int* ys, const float* spec) {

@@ -58,9 +58,10 @@ int pixel_block_columns(int mx, int my, int mz);
 int auto_tile_rows(int H, int W, int block_columns);
 hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s);
 // row sliding DFT of the frame f; also copies f into the delay-ring slot
-// (non-finite samples zeroed and counted in *nonfinite)
+// (non-finite samples zeroed and counted in *nonfinite).  direct: each output
+// is the direct DFT sum of its window instead (Mx = 16 only)
 hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, float* slot,
-                      unsigned long long* nonfinite, hipStream_t s);
+                      unsigned long long* nonfinite, hipStream_t s, bool direct = false);
 // layout: 0 generic observer state [plane][ky][kz]; 1 wave-per-anchor 16x16x8
 // observer state; 2 ring of 2-D spectra [slot][plane][ky] whose newest frame
 // is `newest` (slot newest mod Mz)
@@ -70,7 +71,8 @@ bool pixel16_eligible(int mx, int my, int mz, int nvx, int nvy);
 int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anchor kernel
 // mode: 0 search (or fixed velocity), 1 search + learned features, 2 learned
 // first pass, 3 search refined between grid points, 4 search (or fixed
-// velocity) with the ring of 2-D spectra in place of the observer state
+// velocity) with the ring of 2-D spectra in place of the observer state, 5 as
+// 4 with the column DFT summed directly (no recursion on any axis)
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 // list: [1 + H*W] ints of scratch (count, then the confident anchors)
 hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);

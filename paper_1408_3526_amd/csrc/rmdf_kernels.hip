@@ -33,12 +33,12 @@ namespace rmdf {
 // The single-stream push reads the caller's frame here directly: each block
 // also copies its own columns (non-finite samples zeroed and counted) into
 // the delay-ring slot, so the frame is read once per push.
-template <int MX>
+template <int MX, bool DIRECT>
 __global__ void __launch_bounds__(256) k_row(const float* __restrict__ f, float2* __restrict__ rs,
                                              const float2* __restrict__ twx, int H, int W, float* __restrict__ slot,
                                              unsigned long long* __restrict__ nonfinite) {
   __shared__ __align__(16) char smem[RowShape<MX>::SMEM];
-  row_chunk<MX>(f, rs, twx, H, W, blockIdx.y, blockIdx.x * RCX, smem, nonfinite, slot);
+  row_chunk<MX, DIRECT>(f, rs, twx, H, W, blockIdx.y, blockIdx.x * RCX, smem, nonfinite, slot);
 }
 
 template <int MX, int MY, int MZ>
@@ -109,11 +109,11 @@ static hipError_t launch_pixel_t(const PixArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MX>
+template <int MX, bool DIRECT = false>
 static hipError_t launch_row_t(const float* f, float2* rs, const float2* twx, int H, int W, float* slot,
                                unsigned long long* nonfinite, hipStream_t s) {
   dim3 grid((W + RCX - 1) / RCX, H);
-  hipLaunchKernelGGL((k_row<MX>), grid, dim3(256), 0, s, f, rs, twx, H, W, slot, nonfinite);
+  hipLaunchKernelGGL((k_row<MX, DIRECT>), grid, dim3(256), 0, s, f, rs, twx, H, W, slot, nonfinite);
   return hipGetLastError();
 }
 
@@ -157,7 +157,11 @@ hipError_t launch_pixel(int mx, int my, int mz, const PixArgs& a, hipStream_t s)
 }
 
 hipError_t launch_row(int mx, const float* f, float2* rs, const float2* twx, int H, int W, float* slot,
-                      unsigned long long* nonfinite, hipStream_t s) {
+                      unsigned long long* nonfinite, hipStream_t s, bool direct) {
+  if (direct) {
+    if (mx == 16) return launch_row_t<16, true>(f, rs, twx, H, W, slot, nonfinite, s);
+    return hipErrorInvalidValue;
+  }
   if (mx == 8) return launch_row_t<8>(f, rs, twx, H, W, slot, nonfinite, s);
   if (mx == 16) return launch_row_t<16>(f, rs, twx, H, W, slot, nonfinite, s);
   if (mx == 9) return launch_row_t<9>(f, rs, twx, H, W, slot, nonfinite, s);

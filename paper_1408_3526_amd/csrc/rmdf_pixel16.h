@@ -143,6 +143,12 @@ constexpr int NC_IT = (NV1_MAX + 2) / 3;   // stage-C iterations per lane
 constexpr int ETAB = 8 * 17;        // spatial factors [kx 0..7][ky -8..8], zero outside the band
 constexpr size_t SMEM16 = sizeof(float2) * WAVES * SB_ELEMS + sizeof(float4) * 2 * NV1_MAX * 4 +
                           sizeof(float2) * (LATQ_MAX * MZ + ETAB);
+// mode 5 (direct column DFT): per wavefront, the row spectra of the last My
+// rows ([row mod 16][r] x (plane r, plane r + 4)), and the table w_y^k
+constexpr int CRING = MY * 4;             // float4 per wavefront
+constexpr size_t SMEM16_DIRECT = SMEM16 + sizeof(float4) * WAVES * CRING + sizeof(float2) * MY;
+template <int MODE>
+constexpr size_t smem16_bytes() { return MODE == 5 ? SMEM16_DIRECT : SMEM16; }
 
 // Hann along kx, power spectrum and stage A for one (plane kx, ky) column
 // of kz values.  The centre comes from registers (CREG) or from LDS; the
@@ -267,7 +273,10 @@ static __device__ __forceinline__ void dft8p_scaled(const float2* x, float2* X) 
 // spectra per pixel ([slot][plane][ky], slot = frame mod 8), each frame reads
 // the 7 older slots, writes the new one over the oldest, and forms
 // X_k = (1/8) sum_m w^(k m) S2(t - m) by an 8-point DFT (the observer's
-// posterior in exact arithmetic), halving the state traffic.
+// posterior in exact arithmetic), halving the state traffic; 5 as 4 with the
+// column DFT taken directly as well (sum over the window's My row spectra,
+// kept in LDS), with the row pass also direct: no recursion on any axis, the
+// non-recursive local spectrum as a comparison point.
 template <int MODE>
 static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   lds_v2* s_all = (lds_v2*)(smem);
@@ -285,6 +294,10 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
     const float4* tc = reinterpret_cast<const float4*>(a.tabC);
     for (int i = threadIdx.x; i < 4 * nvy; i += 256) s_tab[i] = v4f{tb[i].x, tb[i].y, tb[i].z, tb[i].w};
     for (int i = threadIdx.x; i < 4 * nvx; i += 256) s_tab[4 * NV1_MAX + i] = v4f{tc[i].x, tc[i].y, tc[i].z, tc[i].w};
+    if (MODE == 5 && threadIdx.x < MY) {
+      lds_v2* wy_tab = (lds_v2*)(smem + SMEM16 + sizeof(float4) * WAVES * CRING);
+      wy_tab[threadIdx.x] = v2f{a.twy[threadIdx.x].x, a.twy[threadIdx.x].y};
+    }
     if (a.gtab != nullptr) {
       for (int i = threadIdx.x; i < a.lat_q * MZ; i += 256) s_g[i] = v2f{a.gtab[i].x, a.gtab[i].y};
       for (int i = threadIdx.x; i < ETAB; i += 256) {
@@ -325,6 +338,10 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
   // frame are zero).  The 16 loads are issued before the recursion, so a tile
   // start costs one memory latency.
   float2 acA = f2(0.f, 0.f), acB = f2(0.f, 0.f);
+  constexpr bool RING = (MODE == 4 || MODE == 5);
+  // mode 5: row spectra of the last My rows of this column, slot = row mod 16
+  lds_v4* s_cr = (lds_v4*)(smem + SMEM16) + wv * CRING;
+  const lds_v2* s_wy = (const lds_v2*)(smem + SMEM16 + sizeof(float4) * WAVES * CRING);
   {
     float2 sA[MY], sB[MY];
 #pragma unroll
@@ -333,10 +350,17 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
       sA[i] = (yy >= 0) ? rsA[(size_t)yy * rstride] : f2(0.f, 0.f);
       sB[i] = (yy >= 0) ? rsB[(size_t)yy * rstride] : f2(0.f, 0.f);
     }
+    if (MODE == 5) {
+      if (ky == 0) {
 #pragma unroll
-    for (int i = 0; i < MY; ++i) {
-      acA = f2(wy.x * acA.x - wy.y * acA.y + sA[i].x, wy.x * acA.y + wy.y * acA.x + sA[i].y);
-      acB = f2(wy.x * acB.x - wy.y * acB.y + sB[i].x, wy.x * acB.y + wy.y * acB.x + sB[i].y);
+        for (int i = 0; i < MY; ++i) s_cr[((y0 - MY + i) & 15) * 4 + r] = v4f{sA[i].x, sA[i].y, sB[i].x, sB[i].y};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < MY; ++i) {
+        acA = f2(wy.x * acA.x - wy.y * acA.y + sA[i].x, wy.x * acA.y + wy.y * acA.x + sA[i].y);
+        acB = f2(wy.x * acB.x - wy.y * acB.y + sB[i].x, wy.x * acB.y + wy.y * acB.x + sB[i].y);
+      }
     }
   }
 
@@ -350,7 +374,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
   const int slot0 = __builtin_amdgcn_readfirstlane(a.tcur & 7);   // mode 4: slot of the new frame
   float2 nA, nB, oA = f2(0.f, 0.f), oB = f2(0.f, 0.f);   // rs(y), rs(y - My)
   {
-    if (MODE == 4) {
+    if (RING) {
       const float2* src = a.st + ((size_t)y0 * a.W + x) * NCOL * MZ;
 #pragma unroll
       for (int m = 1; m < MZ; ++m) {
@@ -368,7 +392,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
     }
     nA = rsA[(size_t)y0 * rstride];
     nB = rsB[(size_t)y0 * rstride];
-    if (y0 >= MY) {
+    if (MODE != 5 && y0 >= MY) {
       oA = rsA[(size_t)(y0 - MY) * rstride];
       oB = rsB[(size_t)(y0 - MY) * rstride];
     }
@@ -377,7 +401,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
   for (int y = y0; y < y1; ++y) {
     const size_t pix = (size_t)y * a.W + x;
     float2 XA[MZ], XB[MZ];
-    if (MODE != 4) {
+    if (!RING) {
 #pragma unroll
       for (int j = 0; j < MZ / 2; ++j) {
         XA[2 * j] = f2(SnA[j].x, SnA[j].y);
@@ -386,13 +410,27 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
         XB[2 * j + 1] = f2(SnB[j].z, SnB[j].w);
       }
     }
-    // ---- column sliding DFT
-    {
+    if (MODE == 5) {
+      // ---- column DFT, direct: sum_m w_y^(ky m) rs(y - m), m = 0 .. 15
+      wave_lds_sync();                   // the previous row's reads of the slot are done
+      if (ky == 0) s_cr[(y & 15) * 4 + r] = v4f{nA.x, nA.y, nB.x, nB.y};
+      wave_lds_sync();
+      acA = f2(0.f, 0.f);
+      acB = f2(0.f, 0.f);
+#pragma unroll
+      for (int m = 0; m < MY; ++m) {
+        const v4f v = s_cr[((y - m) & 15) * 4 + r];
+        const float2 w = ld2(&s_wy[(ky * m) & 15]);
+        acA = f2(acA.x + w.x * v.x - w.y * v.y, acA.y + w.x * v.y + w.y * v.x);
+        acB = f2(acB.x + w.x * v.z - w.y * v.w, acB.y + w.x * v.w + w.y * v.z);
+      }
+    } else {
+      // ---- column sliding DFT
       const float2 iA = f2(nA.x - oA.x, nA.y - oA.y), iB = f2(nB.x - oB.x, nB.y - oB.y);
       acA = f2(wy.x * acA.x - wy.y * acA.y + iA.x, wy.x * acA.y + wy.y * acA.x + iA.y);
       acB = f2(wy.x * acB.x - wy.y * acB.y + iB.x, wy.x * acB.y + wy.y * acB.x + iB.y);
     }
-    if (MODE == 4) {
+    if (RING) {
       // ---- temporal DFT over the ring: the new 2-D spectrum (1/sqrt(16)
       // scale) replaces the oldest slot
       RA[0] = f2(0.25f * acA.x, 0.25f * acA.y);
@@ -500,7 +538,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
     // issued after the loads above, which stage C waits for (vector memory
     // completes in order)
     if (y + 1 < y1) {
-      if (MODE == 4) {
+      if (RING) {
         const float2* src = a.st + (pix + a.W) * NCOL * MZ;
 #pragma unroll
         for (int m = 1; m < MZ; ++m) {
@@ -518,7 +556,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
       }
       nA = rsA[(size_t)(y + 1) * rstride];
       nB = rsB[(size_t)(y + 1) * rstride];
-      if (y + 1 >= MY) {
+      if (MODE != 5 && y + 1 >= MY) {
         oA = rsA[(size_t)(y + 1 - MY) * rstride];
         oB = rsB[(size_t)(y + 1 - MY) * rstride];
       }

@@ -12,7 +12,7 @@ namespace p16 {
 // prefetched state) in registers.
 template <int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_pixel16(PixArgs a) {
-  __shared__ __align__(16) char smem[SMEM16];
+  __shared__ __align__(16) char smem[smem16_bytes<MODE>()];
   const int xblocks = (a.W + WAVES - 1) / WAVES;
   pixel16_tile<MODE>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
 }
@@ -90,7 +90,9 @@ hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   else if (mode == 1) hipLaunchKernelGGL(p16::k_pixel16_feat, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else if (mode == 2) hipLaunchKernelGGL(p16::k_pixel16<2>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else if (mode == 3) hipLaunchKernelGGL(p16::k_pixel16<3>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(p16::k_pixel16<4>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else if (mode == 4) hipLaunchKernelGGL(p16::k_pixel16<4>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else if (mode == 5) hipLaunchKernelGGL(p16::k_pixel16<5>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

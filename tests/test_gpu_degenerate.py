@@ -25,6 +25,7 @@ FORMS = [
     ((16, 16, 8), 2, "observer", "search", (-4, 4, 0.5)),
     ((16, 16, 8), 1, "observer", "search", (-4, 4, 0.5)),
     ((16, 16, 8), 2, "ring", "search", (-4, 4, 0.5)),
+    ((16, 16, 8), 2, "direct", "search", (-4, 4, 0.5)),
     ((16, 16, 8), 2, "observer", "refined", (-4, 4, 0.5)),
     ((8, 8, 4), 0, "observer", "search", (-4, 4, 1.0)),
     ((8, 8, 4), 0, "observer", "refined", (-4, 4, 1.0)),
@@ -34,7 +35,7 @@ FORMS = [
 
 def _filter(b, H, W, M, variant, temporal, vmode, g):
     return b.Filter(H, W, *M, g, g, kernel_variant=variant,
-                    temporal=b.TEMPORAL_RING if temporal == "ring" else b.TEMPORAL_OBSERVER,
+                    temporal={"ring": b.TEMPORAL_RING, "direct": b.TEMPORAL_DIRECT}.get(temporal, b.TEMPORAL_OBSERVER),
                     velocity_mode=b.VEL_REFINED if vmode == "refined" else b.VEL_SEARCH)
 
 

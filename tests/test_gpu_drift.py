@@ -5,9 +5,11 @@ rounding error made at frame t has left the state after Mz more updates
 (Sec. 1; pinned in FP64 by the oracle's deadbeat-recovery test), so its
 error does not grow with the number of frames.  The spatial sliding DFTs
 restart from a direct-DFT seed every 16 columns and every tile of rows.
-Here 2^20 frames (about 1e6) go through both temporal forms (observer state
-and ring of 2-D spectra) and the local spectrum at a few anchors is compared
-with the direct DFT of the current window, in FP64, at checkpoints.
+Here 2^20 frames (about 1e6) go through the three forms of the spectrum
+(observer state; ring of 2-D spectra; the direct form, which has no
+recursion at all and shows the error level without one) and the local
+spectrum at a few anchors is compared with the direct DFT of the current
+window, in FP64, at checkpoints.
 """
 import numpy as np
 import pytest
@@ -52,7 +54,7 @@ def _run(temporal):
     return errs
 
 
-@pytest.mark.parametrize("temporal", [0, 1])
+@pytest.mark.parametrize("temporal", [0, 1, 2])
 def test_no_drift_over_a_million_frames(temporal):
     errs = _run(temporal)
     print("temporal mode %d: relative spectrum error by frame %s" % (temporal, errs))

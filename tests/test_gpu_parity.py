@@ -180,42 +180,54 @@ def test_parity_16x16x8_tiny_frames(orc, H, W, tile, variant):
 
 
 # Temporal ring (the temporal DFT taken directly over a ring of the last Mz
-# 2-D spectra instead of the observer): the same spectrum, so the same bars.
-def test_parity_16x16x8_temporal_ring(orc):
+# 2-D spectra instead of the observer) and the direct form (no recursion on
+# any axis: direct row and column DFT sums as well): the same spectrum, so
+# the same bars.
+TEMPORAL_FORMS = ["ring", "direct"]
+
+
+def _tform(b, name):
+    return {"ring": b.TEMPORAL_RING, "direct": b.TEMPORAL_DIRECT}[name]
+
+
+@pytest.mark.parametrize("form", TEMPORAL_FORMS)
+def test_parity_16x16x8_temporal_forms(orc, form):
     b = _binding()
     sc = scenes.flow_scene(5, H=40, W=47, T=20, n_targets=3, band_width=(8, 12))
     g = scenes.grid(-4, 4, 0.5)
     M = (16, 16, 8)
     xs, ys = np.array([0, 46, 20, 15, 46]), np.array([0, 39, 20, 33, 0])
-    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), tile_rows=16, temporal=b.TEMPORAL_RING)
+    gres = run_gpu(sc.frames, M, g, g, spec_at=(xs, ys), tile_rows=16, temporal=_tform(b, form))
     r = orc.run(_cfg(orc, 40, 47, M, g, g), sc.frames, want_rs=True, want_spec=True)
     check_spec(gres, r, xs, ys)
     check_rs(gres, r)
     check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
 
 
-@pytest.mark.parametrize("H,W,tile", [(3, 5, 32), (17, 1, 4), (1, 9, 8)])
-def test_parity_temporal_ring_tiny_frames(orc, H, W, tile):
+@pytest.mark.parametrize("form", TEMPORAL_FORMS)
+@pytest.mark.parametrize("H,W,tile", [(3, 5, 32), (17, 1, 4), (1, 9, 8), (37, 21, 7)])
+def test_parity_temporal_forms_small_frames(orc, H, W, tile, form):
     b = _binding()
     rng = np.random.default_rng(H * 100 + W + 7)
     fr = (rng.normal(size=(19, H, W)) * 5 + 20).astype(np.float32)
     g = scenes.grid(-2, 2, 1.0)
     M = (16, 16, 8)
-    gres = run_gpu(fr, M, g, g, tile_rows=tile, temporal=b.TEMPORAL_RING)
+    gres = run_gpu(fr, M, g, g, tile_rows=tile, temporal=_tform(b, form))
     r = orc.run(_cfg(orc, H, W, M, g, g), fr, want_rs=True)
     check_rs(gres, r)
     check_velocity_and_output(gres, r, fr, len(g), g, g)
 
 
-def test_temporal_ring_matches_observer_and_pef_null(orc):
-    """The ring and the observer give the same output within FP32 rounding;
-    in fixed-velocity mode the ring's filter nulls translating band-limited
-    clutter like the observer's."""
+@pytest.mark.parametrize("form", TEMPORAL_FORMS)
+def test_temporal_forms_match_observer_and_pef_null(orc, form):
+    """The ring (or the direct form) and the observer give the same output
+    within FP32 rounding; in fixed-velocity mode its filter nulls translating
+    band-limited clutter like the observer's."""
     b = _binding()
     sc = scenes.flow_scene(8, H=64, W=80, T=24, n_targets=4)
     g = scenes.grid(-4, 4, 0.5)
     a = run_gpu(sc.frames, (16, 16, 8), g, g)
-    r = run_gpu(sc.frames, (16, 16, 8), g, g, temporal=b.TEMPORAL_RING)
+    r = run_gpu(sc.frames, (16, 16, 8), g, g, temporal=_tform(b, form))
     rms = float(np.sqrt(np.mean(sc.frames.astype(np.float64) ** 2)))
     # (ties of the argmax, e.g. in the first frames where R vanishes, may
     # resolve differently under different rounding; parity with the oracle,
@@ -235,26 +247,29 @@ def test_temporal_ring_matches_observer_and_pef_null(orc):
             fr[t] += amp * np.cos(2 * np.pi * (kx * (xs - v[0] * t) / M[0] + ky * (ys - v[1] * t) / M[1]) + ph)
     fr = fr.astype(np.float32)
     gres = run_gpu(fr, M, np.zeros(1), np.zeros(1), Bx=B, By=B, velocity_mode=b.VEL_FIXED, fixed_v=v,
-                   temporal=b.TEMPORAL_RING)
+                   temporal=_tform(b, form))
     ref = orc.run(_cfg(orc, H, W, M, np.zeros(1), np.zeros(1), Bx=B, By=B, vmode=2, fvx=v[0], fvy=v[1]), fr)
     frms = float(np.sqrt(np.mean(fr.astype(np.float64) ** 2)))
     assert np.abs(gres["out"] - ref["out"]).max() <= 1e-3 * frms
 
 
-def test_temporal_ring_arguments():
+@pytest.mark.parametrize("form", TEMPORAL_FORMS)
+def test_temporal_forms_arguments(form):
     b = _binding()
     g = scenes.grid(-2, 2, 1.0)
-    for kw in [dict(M=(8, 8, 4)), dict(M=(16, 16, 8), kernel_variant=1),
-               dict(M=(16, 16, 8), velocity_mode=b.VEL_REFINED), dict(M=(16, 16, 8), write_features=True)]:
+    for kw in [dict(M=(8, 8, 4)), dict(M=(9, 9, 5)), dict(M=(16, 16, 8), kernel_variant=1),
+               dict(M=(16, 16, 8), velocity_mode=b.VEL_REFINED), dict(M=(16, 16, 8), velocity_mode=b.VEL_LEARNED),
+               dict(M=(16, 16, 8), write_features=True)]:
         M = kw.pop("M")
         with pytest.raises(b.RmdfError) as e:
-            b.Filter(20, 20, *M, g, g, temporal=b.TEMPORAL_RING, **kw)
+            b.Filter(20, 20, *M, g, g, temporal=_tform(b, form), **kw)
         assert e.value.status == b.RMDF_E_UNSUPPORTED, kw
+    for bad in (3, -1):
+        with pytest.raises(b.RmdfError) as e:
+            b.Filter(20, 20, 16, 16, 8, g, g, temporal=bad)
+        assert e.value.status == b.RMDF_E_INVAL
     with pytest.raises(b.RmdfError) as e:
-        b.Filter(20, 20, 16, 16, 8, g, g, temporal=2)
-    assert e.value.status == b.RMDF_E_INVAL
-    with pytest.raises(b.RmdfError) as e:
-        b.Batch([dict(H=20, W=20, M=(16, 16, 8), gx=g, gy=g)], temporal=b.TEMPORAL_RING)
+        b.Batch([dict(H=20, W=20, M=(16, 16, 8), gx=g, gy=g)], temporal=_tform(b, form))
     assert e.value.status == b.RMDF_E_UNSUPPORTED
 
 
@@ -498,15 +513,18 @@ def test_sampled_parity_640x512_window_16x16x8(orc):
     _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T)
 
 
-def test_sampled_parity_640x512_temporal_ring(orc):
-    """The temporal ring at the benchmark workload's shape, sampled anchors
-    (more frames than the ring holds, so every slot is reused)."""
+@pytest.mark.parametrize("form", TEMPORAL_FORMS)
+def test_sampled_parity_640x512_temporal_forms(orc, form):
+    """The temporal ring and the direct form at the benchmark workload's
+    shape, sampled anchors (more frames than the ring holds, so every slot is
+    reused), against the oracle's per-anchor route (the local spectrum by the
+    direct windowed DFT of eq. 6)."""
     b = _binding()
     T = 20
     sc = scenes.flow_scene(1, H=512, W=640, T=T, n_targets=20)
     g = scenes.grid(-4, 4, 0.5)
     pts = _sample_points(np.random.default_rng(3), 512, 640, 12)
-    _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T, temporal=b.TEMPORAL_RING)
+    _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T, temporal=_tform(b, form))
 
 
 def test_sampled_parity_1280x1024_window_16x16x8(orc):
