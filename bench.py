@@ -27,6 +27,8 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 # reads for a plain copy of known size).  The figure only stands for the
 # kernel source it was taken on: a change to any of these files voids it.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pixel16_{workload}.txt")
+# the same for the temporal-ring and direct-spectrum forms
+TRAFFIC_FILE_FORM = os.path.join(ROOT, "profiles", "traffic_pixel16_{form}_{workload}.txt")
 KERNEL_SOURCES = ["paper_1408_3526_amd/csrc/rmdf_pixel16.h", "paper_1408_3526_amd/csrc/rmdf_pixel16.hip",
                   "paper_1408_3526_amd/csrc/rmdf_kernels.h"]
 
@@ -64,11 +66,13 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kname, workload):
+def measured_traffic(kname, workload, form=None):
     """HBM bytes per launch from the committed counter summary, or None when
     it is absent or was taken on another kernel, workload or source."""
+    path = TRAFFIC_FILE.format(workload=workload) if form is None else TRAFFIC_FILE_FORM.format(form=form,
+                                                                                                workload=workload)
     try:
-        with open(TRAFFIC_FILE.format(workload=workload)) as f:
+        with open(path) as f:
             kv = dict(line.split("=", 1) for line in (ln.strip() for ln in f) if "=" in line and not line.startswith("#"))
     except OSError:
         return None
@@ -100,60 +104,127 @@ def copy_calibration(nbytes=1 << 30, reps=10):
                       "read_plus_write_GBps": 2 * nbytes / (ms / 1e3) / 1e9}), flush=True)
 
 
+def hbm_ceiling(nbytes=1 << 31, reps=5):
+    """Practical HBM ceilings on this GPU from the library's streaming probe
+    (rmdf_hbm_probe): best GB/s over grid sizes and cached / non-temporal
+    access, for read, write and copy (read + write bytes).  The per-pixel
+    kernel reads and writes about equally (the observer state), so its
+    practical ceiling is the copy rate."""
+    import torch
+
+    from paper_1408_3526_amd import binding
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    sink = torch.empty(1 << 16, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+    best = {}
+    for kind, name, moved in ((0, "read", nbytes), (1, "write", nbytes), (2, "copy", 2 * nbytes)):
+        for nt in (False, True):
+            for blocks in (1024, 2048, 4096, 8192, 16384):
+                run = lambda: binding.hbm_probe(kind, src if kind != 1 else None,  # noqa: E731
+                                                sink if kind == 0 else dst, nbytes, blocks, nt)
+                run()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    run()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                gbs = moved * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+                if gbs > best.get(name, {}).get("GBps", 0.0):
+                    best[name] = {"GBps": gbs, "workgroups": blocks, "nontemporal": nt}
+    del src, dst, sink
+    torch.cuda.empty_cache()
+    return best
+
+
 # Batched streams: (count, H, W, window, velocity grid (lo, hi, step), targets)
 BATCH24 = [(8, 256, 320, (8, 8, 4), (-4.0, 4.0, 1.0), 5),
            (8, 512, 640, (16, 16, 8), (-4.0, 4.0, 0.5), 20),
            (8, 1024, 1280, (16, 16, 8), (-4.0, 4.0, 0.5), 50)]
 
 
-def batch_bench(args):
-    """24 streams of three sizes advanced together, one hipGraph launch per
-    step (frames copied into the streams' input slots inside the timed
-    region); tiles chosen by the autotuner first.  Prints one JSON line."""
-    import torch
+def _batch_stream_frames(job):
+    seed, H, W, nfr, nt = job
+    from paper_1408_3526_amd import scenes
+    return scenes.flow_scene(seed, H=H, W=W, T=nfr, n_targets=nt, varying_noise=(H >= 1024)).frames
 
-    from paper_1408_3526_amd import binding, scenes
-    torch.cuda.set_device(0)
-    specs, frames = [], []
+
+def batch_inputs(nfr):
+    """Seeded frames of the 24 streams (own seed, velocity field, band and
+    targets per stream), generated in worker processes; call before the GPU
+    is touched (the workers are forked)."""
+    import concurrent.futures as cf
+
+    from paper_1408_3526_amd import scenes
+    jobs, specs = [], []
     seed = 300
-    nfr = args.frames or 12
-    t0 = time.perf_counter()
     for count, H, W, M, gr, nt in BATCH24:
         g = scenes.grid(*gr)
         for _ in range(count):
             seed += 1
-            fr = scenes.flow_scene(seed, H=H, W=W, T=nfr, n_targets=nt, varying_noise=(H >= 1024)).frames
-            frames.append(torch.from_numpy(fr).cuda())
+            jobs.append((seed, H, W, nfr, nt))
             specs.append(dict(H=H, W=W, M=M, gx=g, gy=g))
-        print("generated %d streams of %dx%d (%.0f s)" % (count, W, H, time.perf_counter() - t0), file=sys.stderr,
-              flush=True)
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        frames = list(ex.map(_batch_stream_frames, jobs))
+    print("generated 24 streams x %d frames (%.0f s)" % (nfr, time.perf_counter() - t0), file=sys.stderr, flush=True)
+    return frames, specs
+
+
+def batch_leg(frames_np, specs, steps, warmup, tune_iters=5):
+    """24 streams of three sizes advanced together, one hipGraph launch per
+    step (frames copied into the streams' input slots inside the timed
+    region); tiles and schedule chosen by the autotuner first.  Aggregate
+    pixel-frames/s, p50/p99 step latency, algorithmic bytes and the share of
+    each tile family in them."""
+    import torch
+
+    from paper_1408_3526_amd import binding
+    torch.cuda.set_device(0)
+    frames = [torch.from_numpy(f).cuda() for f in frames_np]
+    nfr = frames[0].shape[0]
     b = binding.Batch(specs)
-    for i in range(args.warmup):
+    for i in range(warmup):
         b.push([f[i % nfr] for f in frames])
-    report = b.autotune(iters=5)
+    report = b.autotune(iters=tune_iters)
     print(report, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     b.set_timing(True)
     w0 = time.perf_counter()
-    for i in range(args.steps):
-        b.push([f[(args.warmup + i) % nfr] for f in frames])
+    for i in range(steps):
+        b.push([f[(warmup + i) % nfr] for f in frames])
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
     lat = b.latency()
     b.close()
+    del frames
+    torch.cuda.empty_cache()
     px = sum(sp["H"] * sp["W"] for sp in specs)
-    byt = sum(sp["H"] * sp["W"] * algorithmic_bytes_per_pixel_frame(sp["M"], len(sp["gx"]) ** 2) for sp in specs)
+    fam = {}
+    for sp in specs:
+        key = "%dx%d @%dx%dx%d" % (sp["W"], sp["H"], *sp["M"])
+        fam[key] = fam.get(key, 0) + sp["H"] * sp["W"] * algorithmic_bytes_per_pixel_frame(sp["M"], len(sp["gx"]) ** 2)
+    byt = sum(fam.values())
+    return {"value": steps * px / wall, "unit": "pixel-frames/s", "steps": steps, "warmup": warmup,
+            "ms_per_step": 1e3 * wall / steps,
+            "config": {"workload": "24 streams: 8 x 320x256 (8x8x4, 9x9 grid), 8 x 640x512 and 8 x 1280x1024 "
+                                   "(16x16x8, 17x17 grid at 0.5 px/frame)", "frames_distinct": nfr,
+                       "pixels_per_step": px},
+            "latency_ms": {"p50": lat["p50_ms"], "p99": lat["p99_ms"], "mean": lat["mean_ms"]},
+            "algorithmic_GBps": byt * steps / wall / 1e9,
+            "hbm_frac": byt * steps / wall / 1e9 / HBM_PEAK_GBS,
+            "algorithmic_bytes_share": {k: v / byt for k, v in fam.items()},
+            "autotune": report.strip().splitlines()}
+
+
+def batch_bench(args):
+    """The batched-streams workload on its own (--batch24): one JSON line."""
+    frames_np, specs = batch_inputs(args.frames or 12)
+    r = batch_leg(frames_np, specs, args.steps, args.warmup)
     res = {"metric": "batched streams: aggregate pixel-frames/s, per-step latency", "mode": "batch24",
-           "value": args.steps * px / wall, "unit": "pixel-frames/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "24 streams: 8 x 320x256 (8x8x4, 9x9 grid), 8 x 640x512 and 8 x 1280x1024 "
-                                  "(16x16x8, 17x17 grid at 0.5 px/frame)", "frames_distinct": nfr,
-                      "pixels_per_step": px},
-           "latency_ms": {"p50": lat["p50_ms"], "p99": lat["p99_ms"], "mean": lat["mean_ms"]},
-           "algorithmic_GBps": byt * args.steps / wall / 1e9,
-           "hbm_frac": byt * args.steps / wall / 1e9 / HBM_PEAK_GBS,
-           "autotune": report.strip().splitlines()}
+           "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic"}
+    res.update(r)
     print(json.dumps(res), flush=True)
 
 
@@ -170,9 +241,11 @@ def make_scene(wl):
 
 def learned_leg(dev, sc, M, g, steps, warmup):
     """Learned velocity mode (trained weights shipped with the package) on the
-    same frames: pixel-frames/s, and the PEF residual RMS of both modes over
-    the last 10 of the first 40 frames (pixels away from the targets and the
-    frame border).  None when no weights are present."""
+    same frames: pixel-frames/s, and for both modes the PEF residual RMS and
+    the velocity RMSE against the scene's true field over the last 10 of the
+    first 40 frames (anchors whose output pixel is away from the targets and
+    the frame border), and the learned mode's fallback rate.  None when no
+    weights are present."""
     import numpy as np
     import torch
 
@@ -190,18 +263,25 @@ def learned_leg(dev, sc, M, g, steps, warmup):
             f = binding.Filter(H, W, *M, g, g)
         return f
 
-    resid = {}
+    resid, rmse, fallback = {}, {}, {}
     n_eval = min(40, T)
+    dx, dy, dt = M[0] // 2, M[1] // 2, M[2] // 2
+    tv = sc.velocity[np.clip(np.arange(H) - dy, 0, H - 1)][:, np.clip(np.arange(W) - dx, 0, W - 1)]
     for mode in ("plain", "learned"):
         f = make(mode)
-        r = []
+        r, e, fb = [], [], []
         for t in range(n_eval):
             f.push_frame(dev[t])
             if t >= n_eval - 10:
                 out = f.output().cpu().numpy()
-                r.append(learned.residual_rms(out, sc.targets, t - M[2] // 2))
+                vxy, idx = f.velocity()
+                vxy, idx = vxy.cpu().numpy(), idx.cpu().numpy()
+                m = learned.valid_mask(H, W, sc.targets, t - dt, dx=dx, dy=dy)
+                r.append(float(np.sqrt(np.mean(out[m].astype(np.float64) ** 2))))
+                e.append(float(np.sqrt(np.mean(np.sum((vxy[m] - tv[m]) ** 2, -1)))))
+                fb.append(float(np.mean(idx[m] >= 0)))
         f.close()
-        resid[mode] = float(np.mean(r))
+        resid[mode], rmse[mode], fallback[mode] = float(np.mean(r)), float(np.mean(e)), float(np.mean(fb))
     f = make("learned")
     for i in range(warmup):
         f.push_frame(dev[i % T])
@@ -219,7 +299,8 @@ def learned_leg(dev, sc, M, g, steps, warmup):
             "residual_rms": resid["learned"], "plain_residual_rms": resid["plain"],
             "residual_ratio": resid["learned"] / resid["plain"],
             "equal_residual_within_5pct": bool(resid["learned"] <= 1.05 * resid["plain"]),
-            "conf_threshold": 0.9}
+            "velocity_rmse": rmse["learned"], "plain_velocity_rmse": rmse["plain"],
+            "fallback_rate": fallback["learned"], "conf_threshold": 0.9}
 
 
 def refined_leg(dev, sc, M, g, steps, warmup):
@@ -284,22 +365,22 @@ def ring_bytes_per_pixel_frame(M, nv):
     return 4 * Mx * My * Mz + 2 * 4 * nv + 4 + 4 + 4 + 8 + 4
 
 
-def ring_leg(dev, M, g, steps, warmup):
-    """The temporal-ring variant (the temporal DFT taken directly over the last
-    Mz 2-D spectra instead of the observer) on the same frames: pixel-frames/s
-    and its pixel kernel's time against its own algorithmic bytes."""
+def temporal_form_leg(dev, M, g, steps, warmup, temporal, workload=None):
+    """The temporal ring (the temporal DFT taken directly over the last Mz 2-D
+    spectra instead of the observer) or the direct form (no recursion on any
+    axis: direct row and column DFT sums as well) on the same frames:
+    pixel-frames/s, the pixel and row kernels' times, and the pixel kernel's
+    rate against its own algorithmic bytes."""
     import torch
 
     from paper_1408_3526_amd import binding
     if tuple(M) != (16, 16, 8):
         return None
     T, H, W = dev.shape
-    f = binding.Filter(H, W, *M, g, g, temporal=binding.TEMPORAL_RING)
+    f = binding.Filter(H, W, *M, g, g, temporal=temporal)
     for i in range(warmup):
         f.push_frame(dev[i % T])
     torch.cuda.synchronize()
-    f.set_timing(kernels=[0])
-    f.kernel_time(0)
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -309,15 +390,25 @@ def ring_leg(dev, M, g, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # kernel times from a separate pass (each timed launch adds event records)
+    f.set_timing(kernels=[0, 1])
+    f.kernel_time(0)
+    f.kernel_time(1)
+    for i in range(min(steps, 100)):
+        f.push_frame(dev[(warmup + steps + i) % T])
     k = f.kernel_time(0)
+    kr = f.kernel_time(1)
     f.set_timing(False)
     f.close()
     kms = k[0] / max(k[1], 1)
     bpp = ring_bytes_per_pixel_frame(M, len(g) ** 2)
     ach = bpp * H * W / (kms / 1e3) / 1e9
+    form = "ring" if temporal == binding.TEMPORAL_RING else "direct"
+    kname = "k_pixel16<%d>" % (4 if form == "ring" else 5)
     return {"value": steps * H * W / (ms / 1e3), "unit": "pixel-frames/s", "ms_per_step": ms / steps,
-            "kernel_ms": kms, "algorithmic_bytes_per_pixel_frame": bpp, "achieved_GBps": ach,
-            "frac": ach / HBM_PEAK_GBS}
+            "kernel_ms": kms, "row_kernel_ms": kr[0] / max(kr[1], 1),
+            "algorithmic_bytes_per_pixel_frame": bpp, "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic(kname, workload, form) if workload else None}
 
 
 def detection_leg(dev, sc, M, g, guard=2, train=4, ks=(3.0, 3.5, 4.0, 5.0)):
@@ -385,24 +476,34 @@ def detection_leg(dev, sc, M, g, guard=2, train=4, ks=(3.0, 3.5, 4.0, 5.0)):
     return res
 
 
-def cpu_baseline(frames, wl, g, budget_frames=18, crop=(128, 160)):
-    """The FP64 oracle, as it is, on a bounded sample: a crop (rows, columns)
-    of the same frames for budget_frames frames, on all host cores (about
-    10 s of CPU work for the 16x16x8 workloads on 16 cores)."""
+def cpu_baseline(frames, wl, g, strip_rows=64, n_frames=6, runs=3):
+    """The FP64 oracle, as it is, timed on the host's cores over full-width
+    strips of the workload's frames: each run takes strip_rows rows plus the
+    My - 1 rows above them (the rows the windows of the strip's first rows
+    reach into) over the first n_frames frames, and counts only the strip's
+    own pixel-frames; the median over `runs` different strips; all host
+    cores.  Plus a one-thread sample.  About 20 s of CPU work for the
+    640x512 workload on 16 cores."""
     import numpy as np
 
     import oracle
-    sub = np.ascontiguousarray(frames[:budget_frames, :crop[0], :crop[1]])
-    cfg = oracle.Cfg(H=sub.shape[1], W=sub.shape[2], Mx=wl["M"][0], My=wl["M"][1], Mz=wl["M"][2], gx=g, gy=g)
+    T, H, W = frames.shape
+    My = wl["M"][1]
     oracle.lib()
-    t0 = time.perf_counter()
-    oracle.run(cfg, sub)
-    dt = time.perf_counter() - t0
-    n = sub.shape[0] * sub.shape[1] * sub.shape[2]
     cores = oracle.threads()
-    # one thread, on a smaller sample of the same frames (a 48x64 crop, 8 frames)
-    one = np.ascontiguousarray(frames[:8, :48, :64])
-    cfg1 = oracle.Cfg(H=one.shape[1], W=one.shape[2], Mx=wl["M"][0], My=wl["M"][1], Mz=wl["M"][2], gx=g, gy=g)
+    starts = [min(H - strip_rows, max(0, (k + 1) * H // (runs + 1) - strip_rows // 2)) for k in range(runs)]
+    rates = []
+    for y0 in starts:
+        ya = max(0, y0 - (My - 1))
+        sub = np.ascontiguousarray(frames[:n_frames, ya:y0 + strip_rows, :])
+        cfg = oracle.Cfg(H=sub.shape[1], W=W, Mx=wl["M"][0], My=My, Mz=wl["M"][2], gx=g, gy=g)
+        t0 = time.perf_counter()
+        oracle.run(cfg, sub)
+        rates.append(n_frames * strip_rows * W / (time.perf_counter() - t0))
+    value = float(np.median(rates))
+    # one thread, on a smaller sample of the same frames (a 48x64 crop, 4 frames)
+    one = np.ascontiguousarray(frames[:4, :48, :64])
+    cfg1 = oracle.Cfg(H=one.shape[1], W=one.shape[2], Mx=wl["M"][0], My=My, Mz=wl["M"][2], gx=g, gy=g)
     oracle.set_threads(1)
     try:
         t0 = time.perf_counter()
@@ -417,13 +518,13 @@ def cpu_baseline(frames, wl, g, budget_frames=18, crop=(128, 160)):
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": n / dt, "unit": "pixel-frames/s", "cores": cores, "kind": "oracle",
+    return {"value": value, "unit": "pixel-frames/s", "cores": cores, "kind": "oracle",
             "host": {"cpu": model, "usable_cpus": len(os.sched_getaffinity(0))},
-            "sample": "%dx%d crop of the workload's frames, %d frames (%d pixel-frames, %.1f s)"
-                      % (sub.shape[2], sub.shape[1], sub.shape[0], n, dt),
+            "sample": "median of %d runs, each a full-width %d-row strip (+%d rows above, rows %s) of the "
+                      "workload's frames over its first %d frames; rates %s pixel-frames/s"
+                      % (runs, strip_rows, My - 1, starts, n_frames, [round(r) for r in rates]),
             "one_thread": {"value": n1 / dt1, "cores": 1,
-                           "sample": "%dx%d crop, %d frames (%d pixel-frames, %.1f s)"
-                                     % (one.shape[2], one.shape[1], one.shape[0], n1, dt1)}}
+                           "sample": "64x48 crop, 4 frames (%d pixel-frames, %.1f s)" % (n1, dt1)}}
 
 
 def main():
@@ -439,7 +540,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-velocity leg")
     ap.add_argument("--no-refined", action="store_true", help="skip the refined-velocity leg")
     ap.add_argument("--no-detection", action="store_true", help="skip the CFAR detection leg")
-    ap.add_argument("--no-ring", action="store_true", help="skip the temporal-ring variant leg")
+    ap.add_argument("--no-ring", action="store_true",
+                    help="skip the temporal-ring and direct-spectrum variant legs")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-streams leg")
     ap.add_argument("--batch24", action="store_true",
                     help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -462,6 +565,9 @@ def main():
 
     from paper_1408_3526_amd import binding, scenes
 
+    # the batched-streams leg's frames, generated by forked workers before the
+    # GPU is touched
+    batch_in = None if (args.no_batch or args.workload != "640x512") else batch_inputs(4)
     wl = dict(WORKLOADS[args.workload])
     if args.frames:
         wl["frames"] = args.frames
@@ -511,6 +617,7 @@ def main():
     tile_rows = f.tile_rows()
     f.close()
 
+    ceiling = hbm_ceiling()
     px_frames = args.steps * H * W
     value = px_frames / (ms / 1e3)
     bpp = algorithmic_bytes_per_pixel_frame(M, nv)
@@ -536,7 +643,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kname, args.workload),
                      "kernel": kname, "kernel_ms": pix_ms,
-                     "algorithmic_bytes_per_pixel_frame": bpp},
+                     "algorithmic_bytes_per_pixel_frame": bpp,
+                     "practical_peak": ceiling["copy"]["GBps"],
+                     "frac_practical": achieved / ceiling["copy"]["GBps"],
+                     "practical_peak_probe": ceiling},
         "kernel_ms": {"pixel": pix_ms, "row_and_ingest": kms[1][0] / max(kms[1][1], 1)},
         "wall_s": wall,
     }
@@ -552,14 +662,22 @@ def main():
         rf["vs_plain"] = rf["value"] / value
         res["refined"] = rf
     if not args.no_ring:
-        rg = ring_leg(dev, M, g, args.steps, args.warmup)
+        rg = temporal_form_leg(dev, M, g, args.steps, args.warmup, binding.TEMPORAL_RING, args.workload)
         if rg is not None:
             rg["vs_plain"] = rg["value"] / value
             res["temporal_ring"] = rg
+        dr = temporal_form_leg(dev, M, g, args.steps, args.warmup, binding.TEMPORAL_DIRECT, args.workload)
+        if dr is not None:
+            dr["vs_plain"] = dr["value"] / value
+            res["direct_spectrum"] = dr
     if not args.no_detection:
         dl = detection_leg(dev, sc, M, g)
         if dl is not None:
             res["detection"] = dl
+    if batch_in is not None:
+        del dev
+        torch.cuda.empty_cache()
+        res["batch24"] = batch_leg(*batch_in, steps=min(args.steps, 20), warmup=min(args.warmup, 5), tune_iters=3)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(frames, wl, g)
     print(json.dumps(res), flush=True)

@@ -42,6 +42,8 @@ def test_committed_traffic_summaries_match_the_sources():
     sources (else bench.py would report traffic as null)."""
     for wl in ("640x512", "1280x1024"):
         assert bench.measured_traffic("k_pixel16", wl) is not None, wl
+    assert bench.measured_traffic("k_pixel16<4>", "640x512", "ring") is not None
+    assert bench.measured_traffic("k_pixel16<5>", "640x512", "direct") is not None
 
 
 def test_more_than_one_gpu_is_refused():
