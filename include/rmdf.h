@@ -234,6 +234,12 @@ rmdf_status rmdf_mlp_set_weights(rmdf_ctx *ctx, const float *blob, size_t bytes)
 rmdf_status rmdf_features(rmdf_ctx *ctx, void *feat_dev);
 /* Network output of the latest frame, vc_dev[H*W][3] = (vx, vy, confidence). */
 rmdf_status rmdf_learned_output(rmdf_ctx *ctx, float *vc_dev);
+/* The context's network alone on n rows of caller features (feat_dev[n][1152]
+ * BF16, device), with the kernels and launch sequence a learned-mode push
+ * uses: vc_dev[n][3] = (vx, vy, confidence), enqueued on the context stream.
+ * For verification.  Errors: RMDF_E_INVAL (NULL, n < 1), RMDF_E_STATE (not in
+ * learned mode, or no weights), RMDF_E_DEVICE. */
+rmdf_status rmdf_learned_network(rmdf_ctx *ctx, const void *feat_dev, int n, float *vc_dev);
 
 /* Kernels of the learned model, for training (all asynchronous on `stream`,
  * device pointers; BF16 as uint16).  rmdf_mlp_gemm_nt:

@@ -71,6 +71,7 @@ _SIGS = {
     "rmdf_mlp_set_weights": (_I, [_VP, _VP, _SZ]),
     "rmdf_features": (_I, [_VP, _VP]),
     "rmdf_learned_output": (_I, [_VP, _VP]),
+    "rmdf_learned_network": (_I, [_VP, _VP, _I, _VP]),
     "rmdf_mlp_gemm_nt": (_I, [_VP, _I, _VP, _I, _I, _I, _I, _VP, _I, _VP, _I, _VP, _VP, _I, _VP]),
     "rmdf_mlp_transpose": (_I, [_VP, _VP, _I, _I, _VP, _VP]),
     "rmdf_mlp_head": (_I, [_VP, _VP, _VP, _VP, _I, ctypes.c_float, ctypes.c_float, _VP, _VP, _VP, _VP, _VP]),
@@ -297,6 +298,16 @@ class Filter:
         import torch
         out = torch.empty((self.H, self.W, 3), dtype=torch.float32, device="cuda")
         _check(lib().rmdf_learned_output(self.ctx, out.data_ptr()), self.ctx)
+        return out
+
+    def learned_network(self, feat):
+        """rmdf_learned_network: the context's network on caller features
+        (torch BF16 [n, 1152] on the GPU); returns [n, 3] (vx, vy, confidence)."""
+        import torch
+        n = feat.shape[0]
+        ptr = _dev_ptr(feat, torch.bfloat16, n * 1152, "feat")
+        out = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+        _check(lib().rmdf_learned_network(self.ctx, ptr, n, out.data_ptr()), self.ctx)
         return out
 
     def kernel_name(self) -> str:

@@ -475,6 +475,17 @@ static void timed_end(rmdf_ctx* c, EventPair* ev) {
   c->events.push_back(*ev);
 }
 
+// The learned network on n feature rows: two MFMA GEMM layers (bias and ReLU
+// fused, BF16 outputs) into the context's hidden-layer buffers, then the head.
+static rmdf_status run_network(rmdf_ctx* c, const unsigned short* feat, int n, float* vc) {
+  rmdf_status st = rmdf_mlp_gemm_nt(feat, 1152, c->w1, 1152, n, 128, 1152, c->b1, 1, nullptr, 0, nullptr, c->h1, 128,
+                                    c->stream);
+  if (st == RMDF_OK)
+    st = rmdf_mlp_gemm_nt(c->h1, 128, c->w2, 128, n, 64, 128, c->b2, 1, nullptr, 0, nullptr, c->h2, 64, c->stream);
+  if (st == RMDF_OK) st = rmdf_mlp_infer_head(c->h2, c->w3, c->b3, n, vc, c->stream);
+  return st;
+}
+
 rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
   if (!frame) return fail(c, RMDF_E_INVAL, "frame is NULL");
@@ -509,13 +520,8 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   if (mode == 2) {
     // network on every anchor's features (BF16 MFMA, FP32 accumulate), then
     // the background estimate with the chosen velocity
-    const int n = c->H * c->W;
     timed_begin(c, 3, &ev);
-    rmdf_status st = rmdf_mlp_gemm_nt(c->feat, 1152, c->w1, 1152, n, 128, 1152, c->b1, 1, nullptr, 0, nullptr, c->h1,
-                                      128, c->stream);
-    if (st == RMDF_OK)
-      st = rmdf_mlp_gemm_nt(c->h1, 128, c->w2, 128, n, 64, 128, c->b2, 1, nullptr, 0, nullptr, c->h2, 64, c->stream);
-    if (st == RMDF_OK) st = rmdf_mlp_infer_head(c->h2, c->w3, c->b3, n, c->vc, c->stream);
+    const rmdf_status st = run_network(c, c->feat, c->H * c->W, c->vc);
     timed_end(c, &ev);
     if (st != RMDF_OK) return fail(c, st, "network launch failed");
     timed_begin(c, 4, &ev);
@@ -753,6 +759,22 @@ rmdf_status rmdf_learned_output(rmdf_ctx* c, float* vc_dev) {
   if (c->t == 0) return fail(c, RMDF_E_STATE, "no frame pushed yet");
   hipError_t e = hipMemcpyAsync(vc_dev, c->vc, (size_t)c->H * c->W * 3 * 4, hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "copy");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_learned_network(rmdf_ctx* c, const void* feat_dev, int n, float* vc_dev) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (!feat_dev || !vc_dev || n < 1) return fail(c, RMDF_E_INVAL, "bad arguments");
+  if (c->vmode != RMDF_VEL_LEARNED) return fail(c, RMDF_E_STATE, "context is not in learned mode");
+  if (!c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
+  // the hidden-layer buffers hold H*W rows: longer inputs go in pieces
+  const int cap = c->H * c->W;
+  const unsigned short* f = static_cast<const unsigned short*>(feat_dev);
+  for (int r0 = 0; r0 < n; r0 += cap) {
+    const int m = (n - r0 < cap) ? n - r0 : cap;
+    const rmdf_status st = run_network(c, f + (size_t)r0 * 1152, m, vc_dev + (size_t)r0 * 3);
+    if (st != RMDF_OK) return fail(c, st, "network launch failed");
+  }
   return RMDF_OK;
 }
 

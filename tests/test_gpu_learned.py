@@ -180,9 +180,10 @@ def test_features_match_oracle(orc):
 
 
 def test_inference_kernels_within_bounds():
-    """The learned mode's network kernels (the two MFMA GEMM layers and the
-    head, launched as a push launches them) on realistic inputs: every
-    output (vx, vy, confidence) lies inside the interval oracle/mlp.forward_iv
+    """The network's inference kernels on realistic inputs, called directly
+    (two MFMA GEMM layers and the head) and through a learned-mode context
+    (rmdf_learned_network, the launch sequence a push uses): every output
+    (vx, vy, confidence) lies inside the interval oracle/mlp.forward_iv
     derives around the FP64 forward pass of the shipped network."""
     import os
 
@@ -206,12 +207,20 @@ def test_inference_kernels_within_bounds():
     b.mlp_gemm_nt(h1, W2b, bias=f32(params[3]), epi=1, out_bf16=h2)
     b.mlp_infer_head(h2, f32(params[4]), f32(params[5]), vc)
     got = vc.cpu().numpy().astype(np.float64)
+    # the same network through the context (rmdf_learned_network: the
+    # kernels and launch sequence of a learned-mode push), on the same inputs
+    g = scenes.grid(-4, 4, 0.5)
+    f = b.Filter(20, 20, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED)
+    f.set_weights(w)
+    fused = f.learned_network(_bf(X)).cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
+    f.close()
     fw = mlp.forward_iv(X, 0, params)
     Om, Or = fw["O"]
-    assert mlp.within(got[:, :2], Om[:, :2], Or[:, :2]).all()
     clo, chi = mlp.sigmoid_iv(Om[:, 2], Or[:, 2])
-    assert np.all((got[:, 2] >= clo) & (got[:, 2] <= chi))
+    for name, out in (("GEMM kernels", got), ("learned-mode network", fused)):
+        assert mlp.within(out[:, :2], Om[:, :2], Or[:, :2]).all(), name
+        assert np.all((out[:, 2] >= clo) & (out[:, 2] <= chi)), name
     print("output bound: median %.2e, max %.2e (px/frame)" % (np.median(Or[:, :2]), Or[:, :2].max()))
 
 
@@ -320,7 +329,7 @@ def test_sampled_learned_640x512_against_oracle(orc):
     H, W, T = 512, 640, 12
     sc = scenes.flow_scene(2203, H=H, W=W, T=T)
     g = scenes.grid(-4, 4, 0.5)
-    f = b.Filter(H, W, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9)
+    f = b.Filter(H, W, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9, write_features=True)
     f.set_weights(w)
     dev = torch.from_numpy(sc.frames).cuda()
     for t in range(T):
@@ -373,6 +382,66 @@ def test_sampled_learned_640x512_against_oracle(orc):
         assert abs(out[i] - (delayed - ihat)) <= 1e-3 * rms, (x, y, out[i], delayed - ihat)
     print("sampled anchors: %d, confident: %d, output bound median %.3g px/frame"
           % (len(pts), int(confident.sum()), float(np.median(Or[:, :2]))))
+
+
+@pytest.mark.parametrize("H,W", [(45, 70), (29, 37)])
+def test_learned_mode_ragged_tiles_against_oracle(orc, H, W):
+    """Learned mode with work tiles of 7, 16 and 32 rows and frame widths
+    that leave idle columns in the last workgroup, a threshold (0.6) that
+    lets the network decide about half the anchors: each anchor's network
+    output equals, bit for bit, what the network gives on the features the
+    push wrote (rmdf_learned_network); and against the oracle at every
+    anchor, the network's velocity is taken exactly where its confidence
+    reaches the threshold, the fallback is the instantaneous search's first
+    maximum, and the output is the oracle's filter (eq. 4 with eq. 8) at the
+    velocity taken."""
+    import os
+
+    from paper_1408_3526_amd import learned
+    if not os.path.exists(learned.DEFAULT_WEIGHTS):
+        pytest.skip("no trained weights shipped")
+    w = np.load(learned.DEFAULT_WEIGHTS)
+    b = _b()
+    T, thr = 12, 0.6
+    sc = scenes.flow_scene(2301 + H, H=H, W=W, T=T, n_targets=2, band_width=(6, 10))
+    g = scenes.grid(-4, 4, 0.5)
+    dev = torch.from_numpy(sc.frames).cuda()
+    cfg = orc.Cfg(H=H, W=W, Mx=16, My=16, Mz=8, gx=g, gy=g, alpha=0.0)
+    r = orc.run(cfg, sc.frames, want_rs=True, want_spec=True)
+    rs = r["rs_all"][-1]
+    srt = np.sort(rs, -1)
+    scale = np.maximum(np.maximum(np.abs(rs).max(-1), 1e-3 * r["en_all"][-1]), 1e-30)
+    tied = srt[..., -1] - srt[..., -2] <= 1e-4 * scale
+    rms = float(np.sqrt(np.mean(sc.frames[-1].astype(np.float64) ** 2)))
+    for tr in (7, 16, 32):
+        f = b.Filter(H, W, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=thr, tile_rows=tr,
+                     write_features=True)
+        f.set_weights(w)
+        for t in range(T):
+            f.push_frame(dev[t])
+        vxy, idx = f.velocity()
+        feats = f.features()
+        alone = f.learned_network(feats.reshape(H * W, -1)).cpu().numpy().reshape(H, W, 3)
+        out, vxy, idx, vc = f.output().cpu().numpy(), vxy.cpu().numpy(), idx.cpu().numpy(), f.learned_output().cpu().numpy()
+        torch.cuda.synchronize()
+        f.close()
+        assert np.array_equal(vc, alone), tr
+        confident = vc[..., 2] >= thr
+        assert np.array_equal(idx == -2, confident), tr
+        assert 0 < confident.sum() < H * W, (tr, int(confident.sum()))
+        assert np.array_equal(vxy[confident], vc[confident][:, :2]), tr
+        fb = ~confident
+        assert np.all((idx == r["idx"][-1])[fb & ~tied]), tr
+        agree = fb & (idx == r["idx"][-1])
+        assert np.abs(out - r["out"][-1])[agree].max() <= 1e-3 * rms, tr
+        ys, xs = np.nonzero(confident)
+        for y, x in zip(ys, xs):
+            ihat = orc.background(cfg, orc.coeffs(cfg, float(vxy[y, x, 0]), float(vxy[y, x, 1])), r["spec"][y, x])
+            yd, xd = y - cfg.dy, x - cfg.dx
+            delayed = float(sc.frames[T - 1 - cfg.dt, yd, xd]) if (xd >= 0 and yd >= 0) else 0.0
+            assert abs(out[y, x] - (delayed - ihat)) <= 1e-3 * rms, (tr, x, y)
+        print("%dx%d, %d-row tiles: %d of %d anchors took the network's velocity"
+              % (W, H, tr, int(confident.sum()), H * W))
 
 
 def test_refused_push_changes_nothing():
