@@ -21,6 +21,7 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
+from oracle.mlp import TAU_S  # noqa: E402
 from paper_1408_3526_amd import scenes  # noqa: E402
 
 
@@ -96,11 +97,16 @@ def check_rs(g, r):
     return rel
 
 
+# Local spectrum bar: every bin within TAU_S = 1e-6 of the anchor's largest
+# bin (oracle/mlp.py derives it: about 128 sequential FP32 operations per bin,
+# random-walk accumulation sqrt(128) 2^-24 = 6.7e-7, with a 1.5x margin) --
+# a hundred times tighter than the 1e-4 the workload sets.
+
 def check_spec(g, r, xs, ys):
     for i, (x, y) in enumerate(zip(xs, ys)):
         ref = r["spec"][y, x]
         err = np.abs(g["spec"][i] - ref).max()
-        assert err <= 1e-4 * np.abs(ref).max(), (x, y, err, np.abs(ref).max())
+        assert err <= TAU_S * np.abs(ref).max(), (x, y, err, np.abs(ref).max())
 
 
 def test_parity_64x64_window_8x8x4(orc):
@@ -476,7 +482,7 @@ def _sampled_full_size(orc, sc, M, g, pts, T, **kw):
         p = orc.pixel_series(cfg, sc.frames, int(x), int(y), T=T)
         # spectrum of the last frame
         ref = p["S"][-1]
-        assert np.abs(gres["spec"][i] - ref).max() <= 1e-4 * np.abs(ref).max()
+        assert np.abs(gres["spec"][i] - ref).max() <= TAU_S * np.abs(ref).max(), (x, y)
         for t in range(T):
             rs = p["rs"][t]
             srt = np.sort(rs)
