@@ -105,3 +105,15 @@ def test_noalloc_limit_matches_header():
 def test_no_device_reports_device_error(L):
     st, msg = _create(L)
     assert st == -3, (st, msg)
+
+
+def test_hbm_probe_rejects_bad_arguments(L):
+    # checked before any launch: unknown kind, missing buffers, sizes that are
+    # not a positive multiple of 16 bytes, misaligned pointers, no workgroups
+    assert L.rmdf_hbm_probe(3, 16, 16, 1024, 4, 0, None) == -1
+    assert L.rmdf_hbm_probe(2, None, 16, 1024, 4, 0, None) == -1
+    assert L.rmdf_hbm_probe(1, None, None, 1024, 4, 0, None) == -1
+    assert L.rmdf_hbm_probe(2, 16, 16, 1000, 4, 0, None) == -1
+    assert L.rmdf_hbm_probe(2, 16, 16, 0, 4, 0, None) == -1
+    assert L.rmdf_hbm_probe(2, 16, 24, 1024, 4, 0, None) == -1
+    assert L.rmdf_hbm_probe(2, 16, 16, 1024, 0, 0, None) == -1
