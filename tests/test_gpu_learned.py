@@ -475,3 +475,26 @@ def test_refused_push_changes_nothing():
     assert torch.equal(out, out_ref) and torch.equal(vxy, vxy_r) and torch.equal(idx, idx_r)
     f.close()
     ref.close()
+
+
+def test_learned_network_arguments():
+    """rmdf_learned_network refuses a context that is not in learned mode or
+    has no weights, and an empty or missing input, before any launch."""
+    b = _b()
+    g = scenes.grid(-4, 4, 0.5)
+    feat = torch.zeros(16, 1152, dtype=torch.bfloat16, device="cuda")
+    vc = torch.zeros(16, 3, device="cuda")
+    plain = b.Filter(20, 20, 16, 16, 8, g, g)
+    assert b.lib().rmdf_learned_network(plain.ctx, feat.data_ptr(), 16, vc.data_ptr()) == b.RMDF_E_STATE
+    plain.close()
+    f = b.Filter(20, 20, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED)
+    assert b.lib().rmdf_learned_network(f.ctx, feat.data_ptr(), 16, vc.data_ptr()) == b.RMDF_E_STATE
+    f.set_weights(_blob([0.5, -0.25, 3.0]))
+    assert b.lib().rmdf_learned_network(f.ctx, feat.data_ptr(), 0, vc.data_ptr()) == b.RMDF_E_INVAL
+    assert b.lib().rmdf_learned_network(f.ctx, None, 16, vc.data_ptr()) == b.RMDF_E_INVAL
+    out = f.learned_network(feat).cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+    # zero weights but the biases: every row gives (0.5, -0.25, sigmoid(3))
+    assert np.allclose(out[:, 0], 0.5) and np.allclose(out[:, 1], -0.25)
+    assert np.allclose(out[:, 2], 1.0 / (1.0 + np.exp(-3.0)), rtol=1e-6)
