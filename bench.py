@@ -294,8 +294,21 @@ def learned_leg(dev, sc, M, g, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # kernel split (HIP events around each launch, in a separate loop so the
+    # events stay out of the timed one): first pass (spectrum, search,
+    # features), network (count reset + the one network kernel), finish
+    f.set_timing(kernels=[0, 3, 4])
+    for k in (0, 3, 4):
+        f.kernel_time(k)
+    n_split = min(steps, 50)
+    for i in range(n_split):
+        f.push_frame(dev[i % T])
+    split = {name: f.kernel_time(k)[0] / n_split for name, k in (("first_pass", 0), ("network", 3), ("finish", 4))}
     f.close()
+    # the network reads 1152 BF16 features and writes 3 FP32 outputs per anchor
+    net_bytes = H * W * (1152 * 2 + 3 * 4)
     return {"value": steps * H * W / (ms / 1e3), "unit": "pixel-frames/s", "ms_per_step": ms / steps,
+            "kernel_ms": split, "network_GBps": net_bytes / (split["network"] / 1e3) / 1e9,
             "residual_rms": resid["learned"], "plain_residual_rms": resid["plain"],
             "residual_ratio": resid["learned"] / resid["plain"],
             "equal_residual_within_5pct": bool(resid["learned"] <= 1.05 * resid["plain"]),

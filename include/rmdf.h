@@ -203,7 +203,8 @@ rmdf_status rmdf_smoothed_r(rmdf_ctx *ctx, float *rs_dev);
 /* Per-kernel timing with HIP events on the context stream (off by default).
  * which: 0 = pixel kernel, 1 = row sliding-DFT kernel (which also copies the
  * frame into the delay ring), 2 = unused (no separate ingest kernel),
- * 3 = learned-model network (three kernels), 4 = learned-mode finish kernel.
+ * 3 = learned-model network (the confident-anchor count reset and the
+ * network kernel), 4 = learned-mode finish kernel.
  * rmdf_set_timing: mask bit w times kernel w; 0 = off, -1 = all (each timed
  * launch adds two event records to the stream, so time only what is needed).
  * rmdf_kernel_time returns the summed milliseconds and the number of timed
@@ -222,7 +223,7 @@ rmdf_status rmdf_kernel_time(rmdf_ctx *ctx, int which, double *ms, long long *la
  * Layers: 1152 -> 128 (ReLU) -> 64 (ReLU) -> 3, BF16 weights on MFMA with
  * FP32 accumulation for the first two, FP32 for the last.
  * Weight blob (host, FP32, row-major [out][in]): W1 128x1152, b1 128,
- * W2 64x128, b2 64, W3 3x64, b3 3 (bytes = 4 * 155,907).  The velocity index
+ * W2 64x128, b2 64, W3 3x64, b3 3 (bytes = 4 * 156,035).  The velocity index
  * of an anchor that used the network is -2.  The upload is enqueued on the
  * context stream (after the pushes already queued there, which keep the
  * previous weights) and the call returns once it has completed.
@@ -235,10 +236,13 @@ rmdf_status rmdf_features(rmdf_ctx *ctx, void *feat_dev);
 /* Network output of the latest frame, vc_dev[H*W][3] = (vx, vy, confidence). */
 rmdf_status rmdf_learned_output(rmdf_ctx *ctx, float *vc_dev);
 /* The context's network alone on n rows of caller features (feat_dev[n][1152]
- * BF16, device), with the kernels and launch sequence a learned-mode push
- * uses: vc_dev[n][3] = (vx, vy, confidence), enqueued on the context stream.
- * For verification.  Errors: RMDF_E_INVAL (NULL, n < 1), RMDF_E_STATE (not in
- * learned mode, or no weights), RMDF_E_DEVICE. */
+ * BF16, device, 16-byte aligned), with the kernel a learned-mode push uses
+ * (the whole network in one launch; its outputs equal those of
+ * rmdf_mlp_gemm_nt for each hidden layer, ReLU and BF16 output, followed by
+ * rmdf_mlp_infer_head, bit for bit): vc_dev[n][3] = (vx, vy, confidence),
+ * enqueued on the context stream.  For verification.  Errors: RMDF_E_INVAL
+ * (NULL, n < 1, misaligned features), RMDF_E_STATE (not in learned mode, or
+ * no weights), RMDF_E_DEVICE. */
 rmdf_status rmdf_learned_network(rmdf_ctx *ctx, const void *feat_dev, int n, float *vc_dev);
 
 /* Kernels of the learned model, for training (all asynchronous on `stream`,

@@ -58,10 +58,9 @@ struct rmdf_ctx {
   // learned velocity surrogate (16x16x8): features, hidden activations, outputs, weights
   unsigned short* feat = nullptr;  // [HW][1152] BF16
   int* fidx = nullptr;             // [HW] search index (fallback)
-  unsigned short *h1 = nullptr, *h2 = nullptr;   // [HW][128], [HW][64] BF16
   float* vc = nullptr;             // [HW][3] network output (vx, vy, confidence)
   int* conf_list = nullptr;        // [1 + HW]: count, then the confident anchors (pixel index)
-  unsigned short *w1 = nullptr, *w2 = nullptr;   // BF16 [128][1152], [64][128]
+  unsigned short *w1 = nullptr, *w2 = nullptr;   // BF16: W1 in the network kernel's operand order, W2 [64][128]
   float *b1 = nullptr, *b2 = nullptr, *w3 = nullptr, *b3 = nullptr;
   bool weights_set = false;
   unsigned long long* nonfinite = nullptr;
@@ -430,8 +429,6 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   if (needs16 && (e = dalloc(c, &c->feat, HW * 1152)) != hipSuccess) return bail(e, "features");
   if (c->vmode == RMDF_VEL_LEARNED) {
     if ((e = dalloc(c, &c->fidx, HW)) != hipSuccess) return bail(e, "fallback index");
-    if ((e = dalloc(c, &c->h1, HW * 128)) != hipSuccess) return bail(e, "hidden layer");
-    if ((e = dalloc(c, &c->h2, HW * 64)) != hipSuccess) return bail(e, "hidden layer");
     if ((e = dalloc(c, &c->vc, HW * 3)) != hipSuccess) return bail(e, "network output");
     if ((e = dalloc(c, &c->conf_list, HW + 1)) != hipSuccess) return bail(e, "confident-anchor list");
     if ((e = dalloc(c, &c->w1, (size_t)128 * 1152)) != hipSuccess) return bail(e, "weights");
@@ -477,13 +474,10 @@ static void timed_end(rmdf_ctx* c, EventPair* ev) {
 
 // The learned network on n feature rows: two MFMA GEMM layers (bias and ReLU
 // fused, BF16 outputs) into the context's hidden-layer buffers, then the head.
-static rmdf_status run_network(rmdf_ctx* c, const unsigned short* feat, int n, float* vc) {
-  rmdf_status st = rmdf_mlp_gemm_nt(feat, 1152, c->w1, 1152, n, 128, 1152, c->b1, 1, nullptr, 0, nullptr, c->h1, 128,
-                                    c->stream);
-  if (st == RMDF_OK)
-    st = rmdf_mlp_gemm_nt(c->h1, 128, c->w2, 128, n, 64, 128, c->b2, 1, nullptr, 0, nullptr, c->h2, 64, c->stream);
-  if (st == RMDF_OK) st = rmdf_mlp_infer_head(c->h2, c->w3, c->b3, n, vc, c->stream);
-  return st;
+// The network on n feature rows in one kernel; list != nullptr also collects
+// the rows whose confidence clears the context's threshold.
+static hipError_t run_network(rmdf_ctx* c, const unsigned short* feat, int n, float* vc, int* list) {
+  return rmdf::launch_mlp_infer(feat, n, c->w1, c->b1, c->w2, c->b2, c->w3, c->b3, vc, c->conf, list, c->stream);
 }
 
 rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
@@ -520,10 +514,13 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   if (mode == 2) {
     // network on every anchor's features (BF16 MFMA, FP32 accumulate), then
     // the background estimate with the chosen velocity
+    // (the network kernel also lists the anchors whose confidence clears
+    // the threshold; the finish pass filters those)
     timed_begin(c, 3, &ev);
-    const rmdf_status st = run_network(c, c->feat, c->H * c->W, c->vc);
+    e = rmdf::launch_conf_reset(c->conf_list, c->stream);
+    if (e == hipSuccess) e = run_network(c, c->feat, c->H * c->W, c->vc, c->conf_list);
     timed_end(c, &ev);
-    if (st != RMDF_OK) return fail(c, st, "network launch failed");
+    if (e != hipSuccess) return hip_fail(c, e, "network launch");
     timed_begin(c, 4, &ev);
     e = rmdf::launch_finish16(a, c->vc, c->conf, c->conf_list, c->stream);
     timed_end(c, &ev);
@@ -720,7 +717,8 @@ rmdf_status rmdf_mlp_set_weights(rmdf_ctx* c, const float* w, size_t bytes) {
     return (unsigned short)(u >> 16);
   };
   std::vector<unsigned short> w1(n1), w2(n2);
-  for (size_t i = 0; i < n1; ++i) w1[i] = bf(w[i]);
+  for (int col = 0; col < 128; ++col)
+    for (int k = 0; k < 1152; ++k) w1[rmdf::mlp_w1_packed_index(col, k)] = bf(w[(size_t)col * 1152 + k]);
   const float* p = w + n1;
   const float* b1 = p; p += 128;
   for (size_t i = 0; i < n2; ++i) w2[i] = bf(p[i]);
@@ -767,14 +765,9 @@ rmdf_status rmdf_learned_network(rmdf_ctx* c, const void* feat_dev, int n, float
   if (!feat_dev || !vc_dev || n < 1) return fail(c, RMDF_E_INVAL, "bad arguments");
   if (c->vmode != RMDF_VEL_LEARNED) return fail(c, RMDF_E_STATE, "context is not in learned mode");
   if (!c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
-  // the hidden-layer buffers hold H*W rows: longer inputs go in pieces
-  const int cap = c->H * c->W;
-  const unsigned short* f = static_cast<const unsigned short*>(feat_dev);
-  for (int r0 = 0; r0 < n; r0 += cap) {
-    const int m = (n - r0 < cap) ? n - r0 : cap;
-    const rmdf_status st = run_network(c, f + (size_t)r0 * 1152, m, vc_dev + (size_t)r0 * 3);
-    if (st != RMDF_OK) return fail(c, st, "network launch failed");
-  }
+  if (reinterpret_cast<uintptr_t>(feat_dev) & 15) return fail(c, RMDF_E_INVAL, "features not 16-byte aligned");
+  const hipError_t e = run_network(c, static_cast<const unsigned short*>(feat_dev), n, vc_dev, nullptr);
+  if (e != hipSuccess) return hip_fail(c, e, "network launch");
   return RMDF_OK;
 }
 

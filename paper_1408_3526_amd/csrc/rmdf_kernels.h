@@ -74,7 +74,9 @@ int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anch
 // velocity) with the ring of 2-D spectra in place of the observer state, 5 as
 // 4 with the column DFT summed directly (no recursion on any axis)
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
-// list: [1 + H*W] ints of scratch (count, then the confident anchors)
-hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s);
+// learned mode: zero the confident-anchor count list[0] (before the network
+// kernel appends to the list), then filter the listed anchors
+hipError_t launch_conf_reset(int* list, hipStream_t s);
+hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, const int* list, hipStream_t s);
 
 }  // namespace rmdf

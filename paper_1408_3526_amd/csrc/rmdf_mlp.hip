@@ -9,10 +9,17 @@
 //   k_head        layer 3 (64 -> 3), loss and its gradient, dH2, dW3/db3 partial sums
 //   k_infer_head  layer 3 for inference, confidence = sigmoid(logit)
 //   k_adam        Adam update of FP32 master weights + BF16 copy
+//   k_mlp_infer   the whole network for inference in one kernel (features
+//                 streamed into LDS by direct loads, hidden layers kept in LDS,
+//                 confident rows compacted into a list)
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "../../include/rmdf.h"
+#include "rmdf_internal.h"
 
 namespace rmdf {
 namespace mlp {
@@ -282,7 +289,242 @@ __global__ void k_to_bf16(const float* __restrict__ in, unsigned short* __restri
   if (i < n) out[i] = bf16_bits(in[i]);
 }
 
+
+// ---- Inference: the whole network in one kernel -----------------------------
+// vxyc[m] = head(relu(W2 . relu(W1 . f_m + b1) + b2)) for BF16 feature rows f_m
+// (1152 each), with the rounding points and accumulation order of k_gemm_nt
+// (layer 1, ReLU, BF16) -> k_gemm_nt (layer 2, ReLU, BF16) -> k_infer_head:
+// every MFMA chain runs over K in the same ascending 16-wide steps from zero,
+// the bias is added to the finished sum, and the head is the same FP32 fma
+// chain over j, so the outputs equal that three-kernel sequence bit for bit.
+//
+// A workgroup (four wavefronts) takes IBM rows.  Layer 1 streams the rows'
+// features through two LDS stages of 64 features per row, filled by direct
+// global->LDS loads (no register staging; the next slice is in flight while
+// the current one is multiplied); wavefront w owns output columns
+// 32w..32w+31 of every row.  Its W1 operands come from the cache (every
+// workgroup reads all of W1, so it stays L2-resident) in an operand-ordered
+// copy where one wavefront's load is 1 KB contiguous, one slice ahead.  The
+// hidden activations then stay in LDS, and no intermediate touches HBM: per
+// row the kernel reads its 2304 feature bytes and writes 12 bytes (plus a list
+// entry for a confident row).
+constexpr int IK1 = 1152, IN1 = 128, IN2 = 64, INSL = IK1 / BK;   // 18 slices of 64
+constexpr int IBM = 128;                  // rows per workgroup
+constexpr int ISTAGE = IBM * BK;          // BF16 per LDS stage (128 B per row)
+constexpr int IMA = IBM / 32;             // layer-1 accumulators per wavefront
+constexpr int IDPW = IBM / 32;            // 1 KB direct loads per wavefront per slice
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+template <class F, int... I>
+__device__ __forceinline__ void unroll_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+// s_waitcnt vmcnt(0) lgkmcnt(0), then the workgroup barrier.  The direct loads
+// count in vmcnt; lgkmcnt(0) makes this wavefront's LDS reads of the stage
+// about to be refilled complete before any wavefront passes the barrier.  The
+// empty asm statements keep the compiler from moving memory accesses across.
+__device__ __forceinline__ void wait_all_barrier() {
+  __builtin_amdgcn_s_waitcnt((7 << 4));   // vmcnt 0, expcnt free, lgkmcnt 0 (gfx9 fields)
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// W1 operand order: 16-byte unit ((s * 4 + k) * 4 + w) * 64 + lane holds
+// W1[32 w + lane % 32][64 s + 16 k + 8 (lane / 32) .. + 8].
+__host__ __device__ inline size_t w1_packed_index(int col, int kcol) {
+  const int w = col >> 5, r = col & 31, s = kcol / BK, k = (kcol % BK) >> 4, hh = (kcol >> 3) & 1, e = kcol & 7;
+  return ((((size_t)(s * 4 + k) * 4 + w) * 64) + hh * 32 + r) * 8 + e;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_infer(const unsigned short* __restrict__ F, int n,
+                                                   const unsigned short* __restrict__ W1p, const float* __restrict__ b1,
+                                                   const unsigned short* __restrict__ W2, const float* __restrict__ b2,
+                                                   const float* __restrict__ W3, const float* __restrict__ b3,
+                                                   float* __restrict__ vxyc, float thr, int* __restrict__ list) {
+  // two stages as separate objects, so that the compiler can tell a read of
+  // one from a direct load into the other and adds no wait of its own
+  __shared__ __align__(16) unsigned short st0[ISTAGE];
+  __shared__ __align__(16) unsigned short st1[ISTAGE];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int r32 = lane & 31, h = lane >> 5;
+  const int m0 = blockIdx.x * IBM;
+
+  // Stage layout: row r's 64 features are 8 chunks of 16 B, chunk c at slot
+  // c ^ (r & 7) of the row's 128 B (the MFMA operand reads then spread over
+  // all banks).  Direct load q of wavefront w fills rows 8j..8j+7,
+  // j = w * IDPW + q, lane l writing slot l & 7 of row 8j + l / 8, so it
+  // reads chunk (l & 7) ^ (l / 8): eight lanes cover one 128-byte line.
+  // Rows past n re-read row n - 1 (their results are dropped).
+  const unsigned short* src[IDPW];
+#pragma unroll
+  for (int q = 0; q < IDPW; ++q) {
+    const int row = 8 * (wv * IDPW + q) + (lane >> 3);
+    src[q] = F + (size_t)min(m0 + row, n - 1) * IK1 + ((lane & 7) ^ (lane >> 3)) * 8;
+  }
+  auto issue = [&](auto slc) {
+    constexpr int SL = decltype(slc)::value;
+    if constexpr (SL < INSL) {
+      unsigned short* dst = (SL & 1) ? st1 : st0;
+#pragma unroll
+      for (int q = 0; q < IDPW; ++q)   // non-temporal: each feature byte is read once
+        __builtin_amdgcn_global_load_lds((const void*)(src[q] + SL * BK), (lds_void*)(dst + (wv * IDPW + q) * 512),
+                                         16, 0, 2);
+    }
+  };
+  const unsigned short* w1p = W1p + (size_t)(wv * 64 + lane) * 8;
+  bf16x8 bq[2][4];
+  auto load_w1 = [&](auto slc) {
+    constexpr int SL = decltype(slc)::value;
+    if constexpr (SL < INSL) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bq[SL & 1][k] = *reinterpret_cast<const bf16x8*>(w1p + (size_t)(SL * 4 + k) * 2048);
+    }
+  };
+  f32x16 acc[IMA];
+#pragma unroll
+  for (int u = 0; u < IMA; ++u)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[u][i] = 0.f;
+
+  // layer 1: slice SL is multiplied while slice SL + 1 loads
+  issue(std::integral_constant<int, 0>{});
+  load_w1(std::integral_constant<int, 0>{});
+  unroll_seq([&](auto slc) {
+    constexpr int SL = decltype(slc)::value;
+    wait_all_barrier();   // slice SL is in LDS (all wavefronts); slice SL - 1's stage is free
+    load_w1(std::integral_constant<int, SL + 1>{});
+    issue(std::integral_constant<int, SL + 1>{});
+    const unsigned short* a = (SL & 1) ? st1 : st0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int c = 2 * k + h;
+#pragma unroll
+      for (int u = 0; u < IMA; ++u) {
+        const int row = 32 * u + r32;
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(a + row * 64 + ((c ^ (row & 7)) * 8));
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bq[SL & 1][k], acc[u], 0, 0, 0);
+      }
+    }
+  }, std::make_integer_sequence<int, INSL>{});
+  wait_all_barrier();
+
+  // H1 = bf16(relu(acc + b1)) into LDS: 256 B per row, rows 0-15 of each
+  // 32-row block in st0 and rows 16-31 in st1 (local row 16u + row % 16),
+  // chunk c at slot c ^ (local row % 16).  MFMA result layout: column
+  // lane % 32, row (i / 4) * 8 + (lane / 32) * 4 + i % 4.
+  {
+    const int col = 32 * wv + r32;
+    const float bias = b1[col];
+#pragma unroll
+    for (int u = 0; u < IMA; ++u)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        unsigned short* base = (i < 8) ? st0 : st1;
+        const int lr = 16 * u + ((i >> 2) & 1) * 8 + h * 4 + (i & 3);
+        float v = acc[u][i] + bias;
+        v = v > 0.f ? v : 0.f;
+        base[lr * 128 + (((col >> 3) ^ (lr & 15)) * 8) + (col & 7)] = bf16_bits(v);
+      }
+  }
+  wait_all_barrier();
+
+  // layer 2: IBM / 16 units of 32 rows x 32 columns, unit u = w + 4j
+  constexpr int NU = IBM / 16, NJ = (NU + 3) / 4;
+  f32x16 acc2[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int u = wv + 4 * j, rb = u >> 1, cb = u & 1;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc2[j][i] = 0.f;
+    if (u < NU) {
+      const unsigned short* hb = ((r32 < 16) ? st0 : st1) + (16 * rb + (r32 & 15)) * 128;
+      const unsigned short* w2p = W2 + (size_t)(32 * cb + r32) * IN1 + 8 * h;
+      bf16x8 bv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) bv[k] = *reinterpret_cast<const bf16x8*>(w2p + 16 * k);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int c = 2 * k + h;
+        const bf16x8 av = *reinterpret_cast<const bf16x8*>(hb + ((c ^ (r32 & 15)) * 8));
+        acc2[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv[k], acc2[j], 0, 0, 0);
+      }
+    }
+  }
+  wait_all_barrier();
+
+  // H2 = bf16(relu(acc2 + b2)) into st0: 128 B per row, chunk c at slot c ^ (row % 8)
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int u = wv + 4 * j, rb = u >> 1, cb = u & 1;
+    if (u >= NU) continue;
+    const int col = 32 * cb + r32;
+    const float bias = b2[col];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int row = 32 * rb + (i >> 2) * 8 + h * 4 + (i & 3);
+      float v = acc2[j][i] + bias;
+      v = v > 0.f ? v : 0.f;
+      st0[row * 64 + (((col >> 3) ^ (row & 7)) * 8) + (col & 7)] = bf16_bits(v);
+    }
+  }
+  wait_all_barrier();
+
+  // head: thread t < IBM takes row m0 + t (the FP32 chain of k_infer_head)
+  if (tid < IBM) {
+    const int m = m0 + tid;
+    bool ok = false;
+    if (m < n) {
+      float o0 = b3[0], o1 = b3[1], o2 = b3[2];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const uint4 q = *reinterpret_cast<const uint4*>(st0 + tid * 64 + ((c ^ (tid & 7)) * 8));
+        const unsigned int wd[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int jj = 8 * c + e;
+          const float hv = bf16_float((unsigned short)((e & 1) ? (wd[e >> 1] >> 16) : (wd[e >> 1] & 0xffffu)));
+          o0 += W3[jj] * hv;
+          o1 += W3[64 + jj] * hv;
+          o2 += W3[128 + jj] * hv;
+        }
+      }
+      const float conf = 1.f / (1.f + expf(-o2));
+      float* o = vxyc + 3 * (size_t)m;
+      o[0] = o0;
+      o[1] = o1;
+      o[2] = conf;
+      ok = (list != nullptr) && (conf >= thr);
+    }
+    // confident rows into list[1..] (list[0] = count), one atomic per wavefront
+    const unsigned long long mask = __ballot(ok);
+    if (mask) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(list, __popcll(mask));
+      base = __shfl(base, 0, 64);
+      const int before = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0));
+      if (ok) list[1 + base + before] = m;
+    }
+  }
+}
+
 }  // namespace mlp
+
+hipError_t launch_mlp_infer(const unsigned short* feat, int n, const unsigned short* w1p, const float* b1,
+                            const unsigned short* w2, const float* b2, const float* w3, const float* b3, float* vxyc,
+                            float thr, int* list, hipStream_t s) {
+  if (n < 1 || !feat || !w1p || !w2 || !vxyc || ((uintptr_t)feat & 15) || ((uintptr_t)w1p & 15) ||
+      ((uintptr_t)w2 & 15))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(mlp::k_mlp_infer, dim3((n + mlp::IBM - 1) / mlp::IBM), dim3(256), 0, s, feat, n, w1p, b1, w2, b2,
+                     w3, b3, vxyc, thr, list);
+  return hipGetLastError();
+}
+
+size_t mlp_w1_packed_index(int col, int kcol) { return mlp::w1_packed_index(col, kcol); }
+
 }  // namespace rmdf
 
 using namespace rmdf::mlp;

@@ -23,45 +23,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   pixel16_tile<1>(a, a.ring_delayed, blockIdx.x % xblocks, blockIdx.x / xblocks, smem);
 }
 
-// Learned mode, second pass.  k_conf_list compacts the anchors whose
+// Learned mode, second pass.  The network kernel lists the anchors whose
 // confidence clears the threshold (list[0] = count, list[1..] = pixel
-// indices; one atomic per wavefront); k_finish16 then runs one wavefront per
-// listed anchor, its fixed grid striding over the list.
+// indices) after k_conf_reset has zeroed the count; k_finish16 then runs one
+// wavefront per listed anchor, its fixed grid striding over the list.
 __global__ void k_conf_reset(int* list) {
   if (threadIdx.x == 0) list[0] = 0;
-}
-
-// Each thread checks CONF_PER_THREAD anchors (strided by the block size, so
-// every load instruction of a wavefront is one contiguous run) and each
-// wavefront claims its slots with one atomic for all of them: one atomic per
-// 512 anchors on the shared counter instead of one per 64.
-constexpr int CONF_PER_THREAD = 8;
-
-__global__ void __launch_bounds__(256) k_conf_list(const float* __restrict__ vc, long long n, float thr,
-                                                   int* __restrict__ list) {
-  const long long i0 = (long long)blockIdx.x * 256 * CONF_PER_THREAD + threadIdx.x;
-  bool ok[CONF_PER_THREAD];
-  unsigned long long m[CONF_PER_THREAD];
-  int tot = 0;
-#pragma unroll
-  for (int e = 0; e < CONF_PER_THREAD; ++e) {
-    const long long i = i0 + 256LL * e;
-    ok[e] = (i < n) && (vc[3 * i + 2] >= thr);
-    m[e] = __ballot(ok[e]);
-    tot += __popcll(m[e]);
-  }
-  if (tot == 0) return;                   // uniform: tot comes from ballots
-  const int lane = threadIdx.x & 63;
-  int base = 0;
-  if (lane == 0) base = atomicAdd(list, tot);
-  base = __shfl(base, 0, 64);
-#pragma unroll
-  for (int e = 0; e < CONF_PER_THREAD; ++e) {
-    const int before =
-        __builtin_amdgcn_mbcnt_hi((unsigned)(m[e] >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m[e], 0));
-    if (ok[e]) list[1 + base + before] = (int)(i0 + 256LL * e);
-    base += __popcll(m[e]);
-  }
 }
 
 constexpr int FINISH_BLOCKS = 2048;
@@ -96,12 +63,12 @@ hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, int* list, hipStream_t s) {
-  const long long n = (long long)a.H * a.W;
+hipError_t launch_conf_reset(int* list, hipStream_t s) {
   hipLaunchKernelGGL(p16::k_conf_reset, dim3(1), dim3(64), 0, s, list);
-  const long long per_block = 256LL * p16::CONF_PER_THREAD;
-  hipLaunchKernelGGL(p16::k_conf_list, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0, s, vc, n,
-                     thr, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish16(const PixArgs& a, const float* vc, float thr, const int* list, hipStream_t s) {
   hipLaunchKernelGGL(p16::k_finish16, dim3(p16::FINISH_BLOCKS), dim3(256), 0, s, a, vc, thr, list);
   return hipGetLastError();
 }

@@ -222,6 +222,61 @@ def test_inference_kernels_within_bounds():
         assert mlp.within(out[:, :2], Om[:, :2], Or[:, :2]).all(), name
         assert np.all((out[:, 2] >= clo) & (out[:, 2] <= chi)), name
     print("output bound: median %.2e, max %.2e (px/frame)" % (np.median(Or[:, :2]), Or[:, :2].max()))
+    # one kernel against the three: the same bits
+    assert np.array_equal(got, fused)
+
+
+def _network_blob(kind, rng):
+    from paper_1408_3526_amd import learned
+    if kind == "shipped":
+        import os
+        if not os.path.exists(learned.DEFAULT_WEIGHTS):
+            pytest.skip("no trained weights shipped")
+        return np.load(learned.DEFAULT_WEIGHTS).astype(np.float32)
+    parts = [rng.normal(size=(mlp.N_H1, mlp.N_IN)) / np.sqrt(mlp.N_IN), rng.normal(size=mlp.N_H1) * 0.1,
+             rng.normal(size=(mlp.N_H2, mlp.N_H1)) / np.sqrt(mlp.N_H1), rng.normal(size=mlp.N_H2) * 0.1,
+             rng.normal(size=(3, mlp.N_H2)) / np.sqrt(mlp.N_H2), rng.normal(size=3) * 0.1]
+    return np.concatenate([np.ravel(p) for p in parts]).astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [1, 127, 128, 129, 3000, 41000])
+@pytest.mark.parametrize("kind", ["shipped", "random"])
+def test_network_kernel_equals_layer_kernels(n, kind):
+    """The learned-mode network (rmdf_learned_network: one kernel, the
+    features streamed through LDS by direct loads and the hidden layers kept
+    on chip) gives bit for bit what the two GEMM layers with BF16 outputs and
+    the head give when launched one after the other: the same rounding
+    points and the same accumulation order.  Row counts around the 128-row
+    workgroup tile, and a ragged many-tile case longer than the context's
+    frame."""
+    b = _b()
+    rng = np.random.default_rng(1000 + n)
+    w = _network_blob(kind, rng)
+    params = mlp.unpack(w)
+    X = mlp.bf16_round(rng.normal(size=(n, mlp.N_IN)) * 1.5 - np.linspace(0, 6, mlp.N_IN)[None, :] + 3.0)
+    Xd = _bf(X)
+    f32 = lambda a: torch.from_numpy(np.asarray(a, np.float32)).cuda()  # noqa: E731
+    h1 = torch.empty(n, mlp.N_H1, dtype=torch.bfloat16, device="cuda")
+    h2 = torch.empty(n, mlp.N_H2, dtype=torch.bfloat16, device="cuda")
+    vc = torch.empty(n, 3, device="cuda")
+    b.mlp_gemm_nt(Xd, _bf(params[0]), bias=f32(params[1]), epi=1, out_bf16=h1)
+    b.mlp_gemm_nt(h1, _bf(params[2]), bias=f32(params[3]), epi=1, out_bf16=h2)
+    b.mlp_infer_head(h2, f32(params[4]), f32(params[5]), vc)
+    g = scenes.grid(-4, 4, 0.5)
+    f = b.Filter(20, 20, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED)
+    try:
+        f.set_weights(w)
+        one = f.learned_network(Xd)
+        torch.cuda.synchronize()
+    finally:
+        f.close()
+    got, ref = one.cpu().numpy(), vc.cpu().numpy()
+    assert np.array_equal(got.view(np.int32), ref.view(np.int32)), \
+        "%d of %d rows differ" % (int(np.any(got != ref, axis=1).sum()), n)
+    # the case is not degenerate: both ReLU sides and a spread of outputs occur
+    assert 0.01 < float((h1.float() > 0).float().mean()) < 0.99
+    if n > 1:
+        assert np.ptp(ref[:, 0]) > 0 and np.ptp(ref[:, 2]) > 0
 
 
 def _blob(b3):
