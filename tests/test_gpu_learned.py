@@ -534,7 +534,8 @@ def test_refused_push_changes_nothing():
 
 def test_learned_network_arguments():
     """rmdf_learned_network refuses a context that is not in learned mode or
-    has no weights, and an empty or missing input, before any launch."""
+    has no weights, and an empty, missing or misaligned input, before any
+    launch."""
     b = _b()
     g = scenes.grid(-4, 4, 0.5)
     feat = torch.zeros(16, 1152, dtype=torch.bfloat16, device="cuda")
@@ -547,6 +548,8 @@ def test_learned_network_arguments():
     f.set_weights(_blob([0.5, -0.25, 3.0]))
     assert b.lib().rmdf_learned_network(f.ctx, feat.data_ptr(), 0, vc.data_ptr()) == b.RMDF_E_INVAL
     assert b.lib().rmdf_learned_network(f.ctx, None, 16, vc.data_ptr()) == b.RMDF_E_INVAL
+    # the network kernel loads 16-byte pieces: a misaligned feature pointer is refused
+    assert b.lib().rmdf_learned_network(f.ctx, feat.data_ptr() + 2, 15, vc.data_ptr()) == b.RMDF_E_INVAL
     out = f.learned_network(feat).cpu().numpy()
     torch.cuda.synchronize()
     f.close()
