@@ -175,6 +175,8 @@ def test_features_match_oracle(orc):
     S_gpu = f.spectrum([p[0] for p in pts], [p[1] for p in pts]).cpu().numpy()
     torch.cuda.synchronize()
     f.close()
+    del dev
+    torch.cuda.empty_cache()
     cfg = orc.Cfg(H=36, W=40, Mx=16, My=16, Mz=8, gx=g, gy=g)
     _check_features(orc, cfg, sc.frames, pts, F, S_gpu)
 
@@ -374,6 +376,19 @@ def test_sampled_learned_640x512_against_oracle(orc):
     one side of 0.9, that side), otherwise the instantaneous search's grid
     maximum; the output equals the oracle's filter (eq. 4 with eq. 8) at the
     velocity taken."""
+    _sampled_learned(orc, 512, 640, 12, 2203, 17, 34)
+
+
+def test_sampled_learned_2560x2048_against_oracle(orc):
+    """As the 640x512 case on a frame whose features (2560x2048 x 1152 BF16,
+    6.0e9 elements) and observer state pass 2^32 elements: the 64-bit address
+    paths of the first pass, the network kernel, the confident-anchor list
+    and the finish pass, at sampled anchors including the last row and
+    column."""
+    _sampled_learned(orc, 2048, 2560, 9, 2207, 23, 14)
+
+
+def _sampled_learned(orc, H, W, T, seed, pseed, nrand):
     import os
 
     from paper_1408_3526_amd import learned
@@ -381,17 +396,16 @@ def test_sampled_learned_640x512_against_oracle(orc):
         pytest.skip("no trained weights shipped")
     w = np.load(learned.DEFAULT_WEIGHTS)
     b = _b()
-    H, W, T = 512, 640, 12
-    sc = scenes.flow_scene(2203, H=H, W=W, T=T)
+    sc = scenes.flow_scene(seed, H=H, W=W, T=T)
     g = scenes.grid(-4, 4, 0.5)
     f = b.Filter(H, W, 16, 16, 8, g, g, velocity_mode=b.VEL_LEARNED, conf_threshold=0.9, write_features=True)
     f.set_weights(w)
     dev = torch.from_numpy(sc.frames).cuda()
     for t in range(T):
         f.push_frame(dev[t])
-    rng = np.random.default_rng(17)
-    pts = [(0, 0), (W - 1, H - 1), (W - 1, 0), (0, H - 1), (15, 15), (W // 2, H // 2)]
-    pts += [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(34)]
+    rng = np.random.default_rng(pseed)
+    pts = [(0, 0), (W - 1, H - 1), (W - 1, 0), (0, H - 1), (15, 15), (W // 2, H // 2), (W - 3, H - 2)]
+    pts += [(int(rng.integers(0, W)), int(rng.integers(0, H))) for _ in range(nrand)]
     xs = torch.tensor([p[0] for p in pts], device="cuda")
     ys = torch.tensor([p[1] for p in pts], device="cuda")
     F = f.features()[ys, xs].float().cpu().numpy().astype(np.float64)
@@ -402,6 +416,8 @@ def test_sampled_learned_640x512_against_oracle(orc):
     S_gpu = f.spectrum([p[0] for p in pts], [p[1] for p in pts]).cpu().numpy()
     torch.cuda.synchronize()
     f.close()
+    del dev
+    torch.cuda.empty_cache()
 
     cfg = orc.Cfg(H=H, W=W, Mx=16, My=16, Mz=8, gx=g, gy=g, alpha=0.0)
     Xr, Xrad = _check_features(orc, cfg, sc.frames, pts, F, S_gpu)

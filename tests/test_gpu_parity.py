@@ -533,6 +533,63 @@ def test_sampled_parity_640x512_temporal_forms(orc, form):
     _sampled_full_size(orc, sc, (16, 16, 8), g, pts, T, temporal=_tform(b, form))
 
 
+def _sampled_large(orc, sc, M, g, pts, T, **kw):
+    """As _sampled_full_size for frames too large to copy whole to the host:
+    every per-frame result is gathered at the sampled anchors on the GPU."""
+    b = _binding()
+    _, H, W = sc.frames.shape
+    f = b.Filter(H, W, *M, g, g, **kw)
+    dev = torch.from_numpy(np.ascontiguousarray(sc.frames[:T])).cuda()
+    xs = torch.tensor(pts[:, 0], device="cuda", dtype=torch.long)
+    ys = torch.tensor(pts[:, 1], device="cuda", dtype=torch.long)
+    out, idx = [], []
+    for t in range(T):
+        f.push_frame(dev[t])
+        out.append(f.output()[ys, xs].cpu().numpy())
+        idx.append(f.velocity()[1][ys, xs].cpu().numpy())
+    rsm = f.smoothed_r()[ys, xs].cpu().numpy()
+    spec = f.spectrum(list(pts[:, 0]), list(pts[:, 1])).cpu().numpy()
+    torch.cuda.synchronize()
+    f.close()
+    del dev
+    torch.cuda.empty_cache()
+    cfg = _cfg(orc, H, W, M, g, g)
+    agree_n = tot_n = 0
+    for i, (x, y) in enumerate(pts):
+        p = orc.pixel_series(cfg, sc.frames, int(x), int(y), T=T)
+        ref = p["S"][-1]
+        assert np.abs(spec[i] - ref).max() <= TAU_S * np.abs(ref).max(), (x, y)
+        for t in range(T):
+            rs = p["rs"][t]
+            srt = np.sort(rs)
+            scale = max(np.abs(rs).max(), 1e-3 * p["en"][t], 1e-30)
+            tied = srt[-1] - srt[-2] <= 1e-4 * scale
+            gi = idx[t][i]
+            if gi == p["idx"][t]:
+                rms = float(np.sqrt(np.mean(sc.frames[t].astype(np.float64) ** 2)))
+                assert abs(out[t][i] - p["out"][t]) <= 1e-3 * rms
+                agree_n += 1
+            else:
+                assert tied, (x, y, t)
+                assert srt[-1] - rs[gi] <= 2e-4 * scale
+            tot_n += 0 if tied else 1
+        assert np.abs(rsm[i].astype(np.float64) - p["rs"][-1]).max() <= 1e-4 * np.abs(p["rs"][-1]).max()
+    assert agree_n >= 0.999 * tot_n
+
+
+def test_sampled_parity_2560x2048_window_16x16x8(orc):
+    """A frame whose observer state has more than 2^32 complex elements
+    (2560x2048: 43 GB of state, 6 GB of smoothed R), so every 64-bit address
+    path of the 16x16x8 kernels is exercised: sampled anchors, the last rows
+    and columns included, against the oracle."""
+    T = 9
+    sc = scenes.flow_scene(5, H=2048, W=2560, T=T, n_targets=60)
+    g = scenes.grid(-4, 4, 0.5)
+    pts = _sample_points(np.random.default_rng(9), 2048, 2560, 10)
+    pts = np.concatenate([pts, [[2559, 2047 - 5], [2559 - 7, 2047]]])
+    _sampled_large(orc, sc, (16, 16, 8), g, pts, T)
+
+
 def test_sampled_parity_1280x1024_window_16x16x8(orc):
     """Largest single-GPU frame (1280x1024, 10.7 GB observer state)."""
     T = 9
