@@ -171,10 +171,12 @@ def test_parity_16x16x8_coefficient_storage(orc, lo, hi, step, q):
     check_velocity_and_output(gres, r, sc.frames, len(g), g, g)
 
 
-@pytest.mark.parametrize("H,W,tile,variant", [(3, 5, 32, 2), (17, 1, 4, 2), (1, 9, 8, 2), (3, 5, 32, 1), (20, 2, 8, 1)])
+@pytest.mark.parametrize("H,W,tile,variant", [(3, 5, 32, 2), (17, 1, 4, 2), (1, 9, 8, 2), (1, 1, 8, 2), (3, 5, 32, 1),
+                                              (20, 2, 8, 1), (1, 1, 4, 1)])
 def test_parity_16x16x8_tiny_frames(orc, H, W, tile, variant):
     """Frames smaller than the window (every anchor is a border anchor), a
-    single column or row, tiles longer than the frame; both kernels."""
+    single column or row, a single pixel, tiles longer than the frame; both
+    kernels."""
     rng = np.random.default_rng(H * 100 + W + variant)
     fr = (rng.normal(size=(10, H, W)) * 5 + 20).astype(np.float32)
     g = scenes.grid(-2, 2, 1.0)
