@@ -101,6 +101,47 @@ def test_batch_matches_oracle(orc, variant):
     b.close()
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batch_many_tiny_streams_equal_eager(schedule):
+    """36 streams of all three window families at degenerate sizes (single
+    pixels, single rows and columns, frames smaller than the window): the
+    persistent queues hold many one-item streams, and every stream's output,
+    velocity and index still equal its single-stream context's, bit for bit,
+    frame after frame."""
+    from paper_1408_3526_amd import binding
+    rng = np.random.default_rng(36)
+    g1, g5, g25 = scenes.grid(-3, 3, 1.0), scenes.grid(-4, 4, 0.5), scenes.grid(-2, 2, 0.25)
+    shapes = [((8, 8, 4), g1), ((9, 9, 5), g25), ((16, 16, 8), g5)]
+    sizes = [(1, 1), (1, 17), (19, 1), (3, 3), (2, 40), (7, 5)]
+    T = 6
+    st = []
+    for k in range(36):
+        M, g = shapes[k % 3]
+        H, W = sizes[(k // 3) % len(sizes)]
+        fr = (rng.normal(size=(T, H, W)) * 4 + 30).astype(np.float32)
+        st.append(dict(H=H, W=W, M=M, gx=g, gy=g, frames=fr))
+    b = binding.Batch(st, tile_rows=4)
+    b.set_schedule(schedule)
+    singles = [binding.Filter(s["H"], s["W"], *s["M"], s["gx"], s["gy"], tile_rows=4) for s in st]
+    dev = [torch.from_numpy(s["frames"]).cuda() for s in st]
+    for t in range(T):
+        b.push([d[t] for d in dev])
+        for i, sgl in enumerate(singles):
+            sgl.push_frame(dev[i][t])
+        torch.cuda.synchronize()
+        for i, sgl in enumerate(singles):
+            o_b, v_b, i_b = b.output(i)
+            v_s, i_s = sgl.velocity()
+            o_s = sgl.output()
+            torch.cuda.synchronize()
+            assert torch.equal(o_b, o_s), (t, i)
+            assert torch.equal(v_b, v_s), (t, i)
+            assert torch.equal(i_b, i_s), (t, i)
+    for sgl in singles:
+        sgl.close()
+    b.close()
+
+
 def test_batch_autotune_and_latency():
     from paper_1408_3526_amd import binding
     st = _streams()

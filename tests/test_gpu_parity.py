@@ -124,10 +124,10 @@ def test_parity_64x64_window_8x8x4(orc):
     assert np.mean(gres["idx"][-1, 7:, 7:] == r["idx"][-1, 7:, 7:]) >= 0.999
 
 
-@pytest.mark.parametrize("H,W,tile", [(45, 37, 16), (33, 70, 8), (5, 6, 32), (1, 13, 4)])
+@pytest.mark.parametrize("H,W,tile", [(45, 37, 16), (33, 70, 8), (5, 6, 32), (1, 13, 4), (1, 1, 8)])
 def test_parity_ragged_8x8x4(orc, H, W, tile):
     """Frame sizes that leave ragged tails in both tile dimensions, frames
-    smaller than the window, and a single-row frame."""
+    smaller than the window, a single-row frame and a single pixel."""
     rng = np.random.default_rng(H * 100 + W)
     T = 9
     fr = (scenes.gaussian_field(rng, 2 * H + 8, 2 * W + 8, 10.0)[:H, :W] + 100.0)
