@@ -117,3 +117,34 @@ def test_hbm_probe_rejects_bad_arguments(L):
     assert L.rmdf_hbm_probe(2, 16, 16, 0, 4, 0, None) == -1
     assert L.rmdf_hbm_probe(2, 16, 24, 1024, 4, 0, None) == -1
     assert L.rmdf_hbm_probe(2, 16, 16, 1024, 0, 0, None) == -1
+
+def test_header_is_plain_c_and_links(L, tmp_path):
+    """include/rmdf.h compiles as strict C99, and a C program links against
+    the library and gets argument errors back through the ABI without a GPU."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    from paper_1408_3526_amd import binding
+    src = tmp_path / "abi.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include "rmdf.h"
+int main(void) {
+  rmdf_params p;
+  rmdf_ctx *ctx = 0;
+  const float g[3] = {-1.f, 0.f, 1.f};
+  rmdf_params_default(&p);
+  rmdf_status bad = rmdf_create(0, 16, 8, 8, 4, g, 3, g, 3, &p, 0, &ctx);
+  rmdf_status nul = rmdf_push_frame(0, 0);
+  printf("%d %d %d %s\n", (int)bad, (int)nul, ctx == 0, rmdf_last_error(0)[0] ? "msg" : "nomsg");
+  return 0;
+}
+""")
+    exe = tmp_path / "abi"
+    libdir = os.path.dirname(binding.SO_PATH)
+    subprocess.check_call([gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+                           str(src), "-L", libdir, "-lrmdf", "-Wl,-rpath," + libdir, "-o", str(exe)])
+    out = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120).stdout.split()
+    assert out == [str(binding.RMDF_E_INVAL), str(binding.RMDF_E_INVAL), "1", "msg"], out
