@@ -412,6 +412,55 @@ def temporal_form_leg(dev, M, g, steps, warmup, temporal, workload=None):
             "traffic": measured_traffic(kname, workload, form) if workload else None}
 
 
+def pair_bytes_per_pixel_frame(M, nv):
+    """Bytes per pixel and frame when frames go through the per-pixel kernel
+    two at a time: the observer state and the smoothed autocorrelation are
+    read and written once per pair; per frame the same 24 bytes of frame,
+    delayed frame, output, velocity and index (the pair's first frame writes
+    its output only, so 12 of them are not moved for it)."""
+    Mx, My, Mz = M
+    return (2 * 4 * Mx * My * Mz + 2 * 4 * nv) / 2 + (24 + 12) / 2
+
+
+def pairs_leg(dev, M, g, steps, warmup, workload=None):
+    """Frame pairs (rmdf_push_frames, two frames per pass of the per-pixel
+    kernel over the state) on the same frames: pixel-frames/s, the pair
+    kernel's time per pair, and its rate against its own algorithmic bytes."""
+    import torch
+
+    from paper_1408_3526_amd import binding
+    if tuple(M) != (16, 16, 8):
+        return None
+    T, H, W = dev.shape
+    f = binding.Filter(H, W, *M, g, g)
+    pairs = max(1, steps // 2)
+    for i in range(max(1, warmup // 2)):
+        f.push_frames([dev[(2 * i) % T], dev[(2 * i + 1) % T]])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(pairs):
+        f.push_frames([dev[(2 * i) % T], dev[(2 * i + 1) % T]])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    f.set_timing(kernels=[0])
+    f.kernel_time(0)
+    for i in range(min(pairs, 50)):
+        f.push_frames([dev[(2 * i) % T], dev[(2 * i + 1) % T]])
+    k = f.kernel_time(0)
+    f.set_timing(False)
+    f.close()
+    kms = k[0] / max(k[1], 1)
+    bpp = pair_bytes_per_pixel_frame(M, len(g) ** 2)
+    ach = bpp * 2 * H * W / (kms / 1e3) / 1e9
+    return {"value": 2 * pairs * H * W / (ms / 1e3), "unit": "pixel-frames/s", "ms_per_frame": ms / (2 * pairs),
+            "pair_kernel_ms": kms, "algorithmic_bytes_per_pixel_frame": bpp, "achieved_GBps": ach,
+            "frac": ach / HBM_PEAK_GBS,
+            "traffic": measured_traffic("k_pixel16<6>", workload, "pairs") if workload else None}
+
+
 def detection_leg(dev, sc, M, g, guard=2, train=4, ks=(3.0, 3.5, 4.0, 5.0)):
     """Detection stage after the filter: two-sided CA-CFAR (rmdf_cfar) on the
     prediction error of the last 10 of the first 40 frames, and, for
@@ -544,6 +593,7 @@ def main():
     ap.add_argument("--no-ring", action="store_true",
                     help="skip the temporal-ring and direct-spectrum variant legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-streams leg")
+    ap.add_argument("--no-pairs", action="store_true", help="skip the frame-pairs leg")
     ap.add_argument("--batch24", action="store_true",
                     help="batched-streams benchmark (24 streams of three sizes) instead of the single stream")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -677,6 +727,11 @@ def main():
         if dr is not None:
             dr["vs_plain"] = dr["value"] / value
             res["direct_spectrum"] = dr
+    if not args.no_pairs:
+        pr = pairs_leg(dev, M, g, args.steps, args.warmup, args.workload)
+        if pr is not None:
+            pr["vs_plain"] = pr["value"] / value
+            res["frame_pairs"] = pr
     if not args.no_detection:
         dl = detection_leg(dev, sc, M, g)
         if dl is not None:

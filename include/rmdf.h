@@ -153,6 +153,21 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt,
  * RMDF_E_DEVICE (launch failure). */
 rmdf_status rmdf_push_frame(rmdf_ctx *ctx, const float *frame_dev);
 
+/* Push n frames in order (frames_dev: n device pointers, each H*W FP32,
+ * read during the call's kernels).  Where the context allows it (16x16x8
+ * window on the one-wavefront-per-anchor kernel, the observer form, velocity
+ * search or fixed) the frames go through the per-pixel kernel two at a time:
+ * one pass over the observer state and the smoothed R serves both (Sec. 1's
+ * recursion and Sec. 2's smoother advanced twice per pass), so their HBM
+ * traffic per frame halves, at the price of one frame of latency.  The
+ * results are those of n rmdf_push_frame calls, bit for bit.  out_dev: NULL,
+ * or n device pointers (each may be NULL) that receive each frame's output
+ * (H*W FP32, as rmdf_output); rmdf_output and rmdf_velocity then refer to the
+ * last frame.  Every argument and state check precedes the first launch.
+ * Errors: RMDF_E_INVAL (NULL ctx or frame, n < 1), RMDF_E_STATE (learned mode
+ * without weights), RMDF_E_DEVICE. */
+rmdf_status rmdf_push_frames(rmdf_ctx *ctx, int n, const float *const *frames_dev, float *const *out_dev);
+
 /* Copy the velocity field of the latest frame into caller buffers:
  * vxy_dev[H*W*2] = (vx, vy) per anchor; idx_dev[H*W] = candidate index
  * (-1 where a fixed velocity was used); either may be NULL.

@@ -51,6 +51,7 @@ _SIGS = {
     "rmdf_create": (_I, [_I, _I, _I, _I, _I, _VP, _I, _VP, _I, ctypes.POINTER(rmdf_params), _VP,
                          ctypes.POINTER(_VP)]),
     "rmdf_push_frame": (_I, [_VP, _VP]),
+    "rmdf_push_frames": (_I, [_VP, _I, _VP, _VP]),
     "rmdf_velocity": (_I, [_VP, _VP, _VP]),
     "rmdf_output": (_I, [_VP, _VP]),
     "rmdf_frames_pushed": (_I, [_VP, ctypes.POINTER(_LL)]),
@@ -221,6 +222,23 @@ class Filter:
     def push_frame(self, frame):
         import torch
         rmdf_push_frame(self.ctx, _dev_ptr(frame, torch.float32, self.H * self.W, "frame"))
+
+    def push_frames(self, frames, outs=None):
+        """rmdf_push_frames: push frames in order (a list of [H, W] float32
+        CUDA tensors); pairs go through one pass of the per-pixel kernel where
+        the context allows it.  outs: None, or a list of the same length whose
+        entries are None or [H, W] float32 CUDA tensors that receive each
+        frame's output."""
+        import torch
+        n = len(frames)
+        fp = (ctypes.c_void_p * n)(*[_dev_ptr(f, torch.float32, self.H * self.W, "frame") for f in frames])
+        op = None
+        if outs is not None:
+            if len(outs) != n:
+                raise ValueError("outs must have one entry per frame")
+            op = (ctypes.c_void_p * n)(*[None if o is None else _dev_ptr(o, torch.float32, self.H * self.W, "out")
+                                         for o in outs])
+        _check(lib().rmdf_push_frames(self.ctx, n, fp, op), self.ctx)
 
     def output(self, out=None):
         import torch

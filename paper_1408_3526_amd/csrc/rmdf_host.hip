@@ -59,6 +59,10 @@ struct rmdf_ctx {
   unsigned short* feat = nullptr;  // [HW][1152] BF16
   int* fidx = nullptr;             // [HW] search index (fallback)
   float* vc = nullptr;             // [HW][3] network output (vx, vy, confidence)
+  // frame pairs (rmdf_push_frames): the second frame's row spectra, and the
+  // first frame's output when the caller gives no buffer for it
+  float2* rs2 = nullptr;
+  float* out_first = nullptr;
   int* conf_list = nullptr;        // [1 + HW]: count, then the confident anchors (pixel index)
   unsigned short *w1 = nullptr, *w2 = nullptr;   // BF16: W1 in the network kernel's operand order, W2 [64][128]
   float *b1 = nullptr, *b2 = nullptr, *w3 = nullptr, *b3 = nullptr;
@@ -302,6 +306,13 @@ void rmdf_internal_shape(const rmdf_ctx* c, int* mx, int* my, int* mz, int* vari
   *mx = c->MX; *my = c->MY; *mz = c->MZ; *variant = c->variant;
 }
 void rmdf_internal_advance(rmdf_ctx* c) { c->t += 1; }
+
+// Frame pairs run on the 16x16x8 one-wavefront-per-anchor kernel in its
+// observer form with the search or a fixed velocity.
+static bool pairs_supported(const rmdf_ctx* c) {
+  return c->variant == 2 && c->temporal == RMDF_TEMPORAL_OBSERVER &&
+         (c->vmode == RMDF_VEL_SEARCH || c->vmode == RMDF_VEL_FIXED) && !c->write_features;
+}
 void rmdf_internal_set_create_error(const std::string& m) { g_create_error = m; }
 
 extern "C" {
@@ -404,7 +415,9 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
                                                                         : rmdf::pixel_block_columns(Kx, Ky, Kt));
   c->write_features = p.write_features ? 1 : 0;
   c->temporal = p.temporal;
-  c->nring = dt + 1;
+  // one slot beyond the delay: a frame pair stores its second frame before
+  // the pair's first frame has read its delayed sample
+  c->nring = dt + 2;
   // NULL: the device's default (null) stream, which is also torch's default
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->own_stream = false;
@@ -427,6 +440,10 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
   if ((e = dalloc(c, &c->nonfinite, 1)) != hipSuccess) return bail(e, "counter");
   if ((e = build_tables(c, vgrid_x, vgrid_y)) != hipSuccess) return bail(e, "tables");
   if (needs16 && (e = dalloc(c, &c->feat, HW * 1152)) != hipSuccess) return bail(e, "features");
+  if (pairs_supported(c)) {
+    if ((e = dalloc(c, &c->rs2, HW * c->NP)) != hipSuccess) return bail(e, "row spectra");
+    if ((e = dalloc(c, &c->out_first, HW)) != hipSuccess) return bail(e, "output");
+  }
   if (c->vmode == RMDF_VEL_LEARNED) {
     if ((e = dalloc(c, &c->fidx, HW)) != hipSuccess) return bail(e, "fallback index");
     if ((e = dalloc(c, &c->vc, HW * 3)) != hipSuccess) return bail(e, "network output");
@@ -527,6 +544,63 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
     if (e != hipSuccess) return hip_fail(c, e, "finish kernel launch");
   }
   c->t += 1;
+  return RMDF_OK;
+}
+
+// Two frames through one pass of the per-pixel kernel (mode 6).
+static rmdf_status push_pair(rmdf_ctx* c, const float* f0, const float* f1, float* out0) {
+  const size_t HW = (size_t)c->H * c->W;
+  auto slot = [&](long long t) { return c->ring + HW * (size_t)(t % c->nring); };
+  EventPair ev{};
+  hipError_t e;
+  // row pass of each frame into its own row spectra (each also stores its
+  // frame into its delay-ring slot)
+  timed_begin(c, 1, &ev);
+  e = rmdf::launch_row(c->MX, f0, c->rs, c->twx, c->H, c->W, slot(c->t), c->nonfinite, c->stream);
+  if (e == hipSuccess)
+    e = rmdf::launch_row(c->MX, f1, c->rs2, c->twx, c->H, c->W, slot(c->t + 1), c->nonfinite, c->stream);
+  timed_end(c, &ev);
+  if (e != hipSuccess) return hip_fail(c, e, "row kernel launch");
+  rmdf::PixArgs a = rmdf_internal_pixargs(c);
+  a.rs2 = c->rs2;
+  a.ring_delayed = (c->t >= c->dt) ? slot(c->t - c->dt) : nullptr;
+  a.ring_delayed2 = (c->t + 1 >= c->dt) ? slot(c->t + 1 - c->dt) : nullptr;
+  a.out_first = out0 ? out0 : c->out_first;
+  a.tcur = (int)(c->t & 0x3fffffff);
+  timed_begin(c, 0, &ev);
+  e = rmdf::launch_pixel16(a, 6, c->stream);
+  timed_end(c, &ev);
+  if (e != hipSuccess) return hip_fail(c, e, "pixel kernel launch");
+  c->t += 2;
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_push_frames(rmdf_ctx* c, int n, const float* const* frames, float* const* outs) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (n < 1 || !frames) return fail(c, RMDF_E_INVAL, "n must be >= 1 and frames non-NULL");
+  for (int i = 0; i < n; ++i)
+    if (!frames[i]) return fail(c, RMDF_E_INVAL, "frame is NULL");
+  if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
+  const size_t bytes = (size_t)c->H * c->W * sizeof(float);
+  for (int i = 0; i < n;) {
+    float* o0 = outs ? outs[i] : nullptr;
+    if (pairs_supported(c) && i + 1 < n) {
+      const rmdf_status st = push_pair(c, frames[i], frames[i + 1], o0);
+      if (st != RMDF_OK) return st;
+      float* o1 = outs ? outs[i + 1] : nullptr;
+      hipError_t e;
+      if (o1 && (e = hipMemcpyAsync(o1, c->out, bytes, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy");
+      i += 2;
+    } else {
+      const rmdf_status st = rmdf_push_frame(c, frames[i]);
+      if (st != RMDF_OK) return st;
+      hipError_t e;
+      if (o0 && (e = hipMemcpyAsync(o0, c->out, bytes, hipMemcpyDeviceToDevice, c->stream)) != hipSuccess)
+        return hip_fail(c, e, "copy");
+      i += 1;
+    }
+  }
   return RMDF_OK;
 }
 

@@ -48,6 +48,11 @@ struct PixArgs {
   const int* latq;             // [nv+1] (nx << 16) | (ny & 0xffff); entry nv = fixed velocity
   int lat_q;                   // 16s
   int tcur;                    // index of the frame being pushed (ring slot = tcur mod Mz)
+  // frame pairs (16x16x8 kernel, mode 6): the second frame's row spectra and
+  // delayed input; the first frame's output goes to out_first
+  const float2* rs2;
+  const float* ring_delayed2;
+  float* out_first;
 };
 
 bool shape_supported(int mx, int my, int mz);
@@ -72,7 +77,8 @@ int p16_block_columns();   // anchors per workgroup of the 16x16x8 wave-per-anch
 // mode: 0 search (or fixed velocity), 1 search + learned features, 2 learned
 // first pass, 3 search refined between grid points, 4 search (or fixed
 // velocity) with the ring of 2-D spectra in place of the observer state, 5 as
-// 4 with the column DFT summed directly (no recursion on any axis)
+// 4 with the column DFT summed directly (no recursion on any axis), 6 as 0 for
+// two frames in one pass over the state (rs: first frame, rs2: second)
 hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s);
 // learned mode: zero the confident-anchor count list[0] (before the network
 // kernel appends to the list), then filter the listed anchors

@@ -21,6 +21,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rmdf_kernels.h"
 #include "rmdf_refine.h"
 
@@ -364,6 +366,25 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
     }
   }
 
+  // mode 6: the pair's second frame has its own row spectra and column SDFT
+  float2 acA2 = f2(0.f, 0.f), acB2 = f2(0.f, 0.f);
+  const float2* rsA2 = (MODE == 6) ? a.rs2 + (size_t)x * 8 + pA : rsA;
+  const float2* rsB2 = (MODE == 6) ? a.rs2 + (size_t)x * 8 + pB : rsB;
+  if (MODE == 6) {
+    float2 sA[MY], sB[MY];
+#pragma unroll
+    for (int i = 0; i < MY; ++i) {
+      const int yy = y0 - MY + i;
+      sA[i] = (yy >= 0) ? rsA2[(size_t)yy * rstride] : f2(0.f, 0.f);
+      sB[i] = (yy >= 0) ? rsB2[(size_t)yy * rstride] : f2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < MY; ++i) {
+      acA2 = f2(wy.x * acA2.x - wy.y * acA2.y + sA[i].x, wy.x * acA2.y + wy.y * acA2.x + sA[i].y);
+      acB2 = f2(wy.x * acB2.x - wy.y * acB2.y + sB[i].x, wy.x * acB2.y + wy.y * acB2.x + sB[i].y);
+    }
+  }
+
   // Rows are software-pipelined: the observer state and row-spectrum samples
   // of row y + 1 are loaded as soon as row y has staged its planes in LDS, so
   // their HBM latency hides behind the flow stages of row y.  State layout:
@@ -373,6 +394,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
   float2 RA[MZ], RB[MZ];                                 // mode 4: S2(t - m) of the row, m = 0..7
   const int slot0 = __builtin_amdgcn_readfirstlane(a.tcur & 7);   // mode 4: slot of the new frame
   float2 nA, nB, oA = f2(0.f, 0.f), oB = f2(0.f, 0.f);   // rs(y), rs(y - My)
+  float2 nA2 = f2(0.f, 0.f), nB2 = f2(0.f, 0.f), oA2 = f2(0.f, 0.f), oB2 = f2(0.f, 0.f);   // mode 6
   {
     if (RING) {
       const float2* src = a.st + ((size_t)y0 * a.W + x) * NCOL * MZ;
@@ -396,6 +418,14 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
       oA = rsA[(size_t)(y0 - MY) * rstride];
       oB = rsB[(size_t)(y0 - MY) * rstride];
     }
+    if (MODE == 6) {
+      nA2 = rsA2[(size_t)y0 * rstride];
+      nB2 = rsB2[(size_t)y0 * rstride];
+      if (y0 >= MY) {
+        oA2 = rsA2[(size_t)(y0 - MY) * rstride];
+        oB2 = rsB2[(size_t)(y0 - MY) * rstride];
+      }
+    }
   }
 
   for (int y = y0; y < y1; ++y) {
@@ -410,369 +440,393 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
         XB[2 * j + 1] = f2(SnB[j].z, SnB[j].w);
       }
     }
-    if (MODE == 5) {
-      // ---- column DFT, direct: sum_m w_y^(ky m) rs(y - m), m = 0 .. 15
-      wave_lds_sync();                   // the previous row's reads of the slot are done
-      if (ky == 0) s_cr[(y & 15) * 4 + r] = v4f{nA.x, nA.y, nB.x, nB.y};
-      wave_lds_sync();
-      acA = f2(0.f, 0.f);
-      acB = f2(0.f, 0.f);
+    // the row's work for one frame; mode 6 runs it for both frames of a
+    // pair: the second frame's observer starts from the first's posterior
+    // (still in registers), its smoothing from the first's smoothed R, and
+    // the state and smoothed R are stored once, after the second
+    float rprev[NC_IT];
+    auto frame = [&](auto fc) {
+      constexpr int F = decltype(fc)::value;
+      constexpr bool LAST = (MODE != 6) || (F == 1);
+      float2& cA = F ? acA2 : acA;
+      float2& cB = F ? acB2 : acB;
+      float2& cnA = F ? nA2 : nA;
+      float2& cnB = F ? nB2 : nB;
+      float2& coA = F ? oA2 : oA;
+      float2& coB = F ? oB2 : oB;
+      const float2* frA = F ? rsA2 : rsA;
+      const float2* frB = F ? rsB2 : rsB;
+      const float* rdel = F ? a.ring_delayed2 : ring_delayed;
+      if (MODE == 5) {
+        // ---- column DFT, direct: sum_m w_y^(ky m) rs(y - m), m = 0 .. 15
+        wave_lds_sync();                   // the previous row's reads of the slot are done
+        if (ky == 0) s_cr[(y & 15) * 4 + r] = v4f{cnA.x, cnA.y, cnB.x, cnB.y};
+        wave_lds_sync();
+        cA = f2(0.f, 0.f);
+        cB = f2(0.f, 0.f);
 #pragma unroll
-      for (int m = 0; m < MY; ++m) {
-        const v4f v = s_cr[((y - m) & 15) * 4 + r];
-        const float2 w = ld2(&s_wy[(ky * m) & 15]);
-        acA = f2(acA.x + w.x * v.x - w.y * v.y, acA.y + w.x * v.y + w.y * v.x);
-        acB = f2(acB.x + w.x * v.z - w.y * v.w, acB.y + w.x * v.w + w.y * v.z);
+        for (int m = 0; m < MY; ++m) {
+          const v4f v = s_cr[((y - m) & 15) * 4 + r];
+          const float2 w = ld2(&s_wy[(ky * m) & 15]);
+          cA = f2(cA.x + w.x * v.x - w.y * v.y, cA.y + w.x * v.y + w.y * v.x);
+          cB = f2(cB.x + w.x * v.z - w.y * v.w, cB.y + w.x * v.w + w.y * v.z);
+        }
+      } else {
+        // ---- column sliding DFT
+        const float2 iA = f2(cnA.x - coA.x, cnA.y - coA.y), iB = f2(cnB.x - coB.x, cnB.y - coB.y);
+        cA = f2(wy.x * cA.x - wy.y * cA.y + iA.x, wy.x * cA.y + wy.y * cA.x + iA.y);
+        cB = f2(wy.x * cB.x - wy.y * cB.y + iB.x, wy.x * cB.y + wy.y * cB.x + iB.y);
       }
-    } else {
-      // ---- column sliding DFT
-      const float2 iA = f2(nA.x - oA.x, nA.y - oA.y), iB = f2(nB.x - oB.x, nB.y - oB.y);
-      acA = f2(wy.x * acA.x - wy.y * acA.y + iA.x, wy.x * acA.y + wy.y * acA.x + iA.y);
-      acB = f2(wy.x * acB.x - wy.y * acB.y + iB.x, wy.x * acB.y + wy.y * acB.x + iB.y);
-    }
-    if (RING) {
-      // ---- temporal DFT over the ring: the new 2-D spectrum (1/sqrt(16)
-      // scale) replaces the oldest slot
-      RA[0] = f2(0.25f * acA.x, 0.25f * acA.y);
-      RB[0] = f2(0.25f * acB.x, 0.25f * acB.y);
-      dft8p_scaled(RA, XA);
-      dft8p_scaled(RB, XB);
-      float2* dst = a.st + pix * NCOL * MZ + slot0 * NCOL;
-      st2_stream(&dst[pA * MY + ky], RA[0]);
-      st2_stream(&dst[pB * MY + ky], RB[0]);
-    } else {
-      // ---- deadbeat observer (posterior rotated, innovation shared by all kz)
-      float2 sA = f2(0.f, 0.f), sB2 = f2(0.f, 0.f);
+      if (RING) {
+        // ---- temporal DFT over the ring: the new 2-D spectrum (1/sqrt(16)
+        // scale) replaces the oldest slot
+        RA[0] = f2(0.25f * cA.x, 0.25f * cA.y);
+        RB[0] = f2(0.25f * cB.x, 0.25f * cB.y);
+        dft8p_scaled(RA, XA);
+        dft8p_scaled(RB, XB);
+        float2* dst = a.st + pix * NCOL * MZ + slot0 * NCOL;
+        st2_stream(&dst[pA * MY + ky], RA[0]);
+        st2_stream(&dst[pB * MY + ky], RB[0]);
+      } else {
+        // ---- deadbeat observer (posterior rotated, innovation shared by all kz)
+        float2 sA = f2(0.f, 0.f), sB2 = f2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) {
+          XA[k] = rot8(XA[k], k);
+          XB[k] = rot8(XB[k], k);
+          sA = f2(sA.x + XA[k].x, sA.y + XA[k].y);
+          sB2 = f2(sB2.x + XB[k].x, sB2.y + XB[k].y);
+        }
+        // s2 = ac / 4 (1/sqrt(16)); e = (s2 - sum) / 8
+        const float2 eA = f2((0.25f * cA.x - sA.x) * 0.125f, (0.25f * cA.y - sA.y) * 0.125f);
+        const float2 eB = f2((0.25f * cB.x - sB2.x) * 0.125f, (0.25f * cB.y - sB2.y) * 0.125f);
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) {
+          XA[k] = f2(XA[k].x + eA.x, XA[k].y + eA.y);
+          XB[k] = f2(XB[k].x + eB.x, XB[k].y + eB.y);
+        }
+        float4* dst = reinterpret_cast<float4*>(a.st + pix * NCOL * MZ);
+#pragma unroll
+        for (int j = 0; j < (LAST ? MZ / 2 : 0); ++j) {
+          st_stream(&dst[j * NCOL + pA * MY + ky], XA[2 * j].x, XA[2 * j].y, XA[2 * j + 1].x, XA[2 * j + 1].y);
+          st_stream(&dst[j * NCOL + pB * MY + ky], XB[2 * j].x, XB[2 * j].y, XB[2 * j + 1].x, XB[2 * j + 1].y);
+        }
+      }
+      // ---- high-pass + Hann along kz (2X(k) - X(k-1) - X(k+1); the 1/4 per
+      // axis is folded into the stage-A weights)
+      float2 HA[MZ], HB[MZ];
+      {
+        float2 V[MZ];
+        const bool dc = (lane == 0);       // plane 0 (kx = 0 | kx = 8 packed), ky = 0
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) {
+          const float2 m = XA[(MZ - k) & 7];
+          // drop the kx = 0 part: C - (C + conj C(-kz)) / 2
+          V[k] = dc ? f2(0.5f * (XA[k].x - m.x), 0.5f * (XA[k].y + m.y)) : XA[k];
+        }
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) {
+          const float2 l = V[(k + 7) & 7], rr = V[(k + 1) & 7];
+          HA[k] = f2(2.f * V[k].x - l.x - rr.x, 2.f * V[k].y - l.y - rr.y);
+          const float2 lb = XB[(k + 7) & 7], rb = XB[(k + 1) & 7];
+          HB[k] = f2(2.f * XB[k].x - lb.x - rb.x, 2.f * XB[k].y - lb.y - rb.y);
+        }
+      }
+      // ---- Hann along ky: the neighbours are the adjacent lanes of the row
 #pragma unroll
       for (int k = 0; k < MZ; ++k) {
-        XA[k] = rot8(XA[k], k);
-        XB[k] = rot8(XB[k], k);
-        sA = f2(sA.x + XA[k].x, sA.y + XA[k].y);
-        sB2 = f2(sB2.x + XB[k].x, sB2.y + XB[k].y);
+        const float2 dA = dpp2<ROR1>(HA[k]), uA = dpp2<ROR15>(HA[k]);
+        HA[k] = f2(2.f * HA[k].x - dA.x - uA.x, 2.f * HA[k].y - dA.y - uA.y);
+        const float2 dB = dpp2<ROR1>(HB[k]), uB = dpp2<ROR15>(HB[k]);
+        HB[k] = f2(2.f * HB[k].x - dB.x - uB.x, 2.f * HB[k].y - dB.y - uB.y);
       }
-      // s2 = ac / 4 (1/sqrt(16)); e = (s2 - sum) / 8
-      const float2 eA = f2((0.25f * acA.x - sA.x) * 0.125f, (0.25f * acA.y - sA.y) * 0.125f);
-      const float2 eB = f2((0.25f * acB.x - sB2.x) * 0.125f, (0.25f * acB.y - sB2.y) * 0.125f);
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        XA[k] = f2(XA[k].x + eA.x, XA[k].y + eA.y);
-        XB[k] = f2(XB[k].x + eB.x, XB[k].y + eB.y);
-      }
-      float4* dst = reinterpret_cast<float4*>(a.st + pix * NCOL * MZ);
-#pragma unroll
-      for (int j = 0; j < MZ / 2; ++j) {
-        st_stream(&dst[j * NCOL + pA * MY + ky], XA[2 * j].x, XA[2 * j].y, XA[2 * j + 1].x, XA[2 * j + 1].y);
-        st_stream(&dst[j * NCOL + pB * MY + ky], XB[2 * j].x, XB[2 * j].y, XB[2 * j + 1].x, XB[2 * j + 1].y);
-      }
-    }
-    // ---- high-pass + Hann along kz (2X(k) - X(k-1) - X(k+1); the 1/4 per
-    // axis is folded into the stage-A weights)
-    float2 HA[MZ], HB[MZ];
-    {
-      float2 V[MZ];
-      const bool dc = (lane == 0);       // plane 0 (kx = 0 | kx = 8 packed), ky = 0
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const float2 m = XA[(MZ - k) & 7];
-        // drop the kx = 0 part: C - (C + conj C(-kz)) / 2
-        V[k] = dc ? f2(0.5f * (XA[k].x - m.x), 0.5f * (XA[k].y + m.y)) : XA[k];
-      }
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const float2 l = V[(k + 7) & 7], rr = V[(k + 1) & 7];
-        HA[k] = f2(2.f * V[k].x - l.x - rr.x, 2.f * V[k].y - l.y - rr.y);
-        const float2 lb = XB[(k + 7) & 7], rb = XB[(k + 1) & 7];
-        HB[k] = f2(2.f * XB[k].x - lb.x - rb.x, 2.f * XB[k].y - lb.y - rb.y);
-      }
-    }
-    // ---- Hann along ky: the neighbours are the adjacent lanes of the row
-#pragma unroll
-    for (int k = 0; k < MZ; ++k) {
-      const float2 dA = dpp2<ROR1>(HA[k]), uA = dpp2<ROR15>(HA[k]);
-      HA[k] = f2(2.f * HA[k].x - dA.x - uA.x, 2.f * HA[k].y - dA.y - uA.y);
-      const float2 dB = dpp2<ROR1>(HB[k]), uB = dpp2<ROR15>(HB[k]);
-      HB[k] = f2(2.f * HB[k].x - dB.x - uB.x, 2.f * HB[k].y - dB.y - uB.y);
-    }
-    // ---- stage the y,z-windowed planes in LDS, then unpack plane 0:
-    // S(0) = (C + conj C(-k)) / 2, S(8) = (C - conj C(-k)) / 2j
-    wave_lds_sync();                     // previous row's stage C reads are done
-#pragma unroll
-    for (int k = 0; k < MZ; k += 2) {
-      st4(&s_b[sb_idx(pA, ky, k)], HA[k].x, HA[k].y, HA[k + 1].x, HA[k + 1].y);
-      st4(&s_b[sb_idx(pB, ky, k)], HB[k].x, HB[k].y, HB[k + 1].x, HB[k + 1].y);
-    }
-    wave_lds_sync();
-    if (r == 0) {
-      // every read of plane 0 precedes every write to it (one wavefront,
-      // program order)
-      float2 w[MZ];
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) w[k] = ld2(&s_b[sb_idx(0, (MY - ky) & 15, (MZ - k) & 7)]);
+      // ---- stage the y,z-windowed planes in LDS, then unpack plane 0:
+      // S(0) = (C + conj C(-k)) / 2, S(8) = (C - conj C(-k)) / 2j
+      wave_lds_sync();                     // previous row's stage C reads are done
 #pragma unroll
       for (int k = 0; k < MZ; k += 2) {
-        const float2 u0 = HA[k], u1 = HA[k + 1], w0 = w[k], w1 = w[k + 1];
-        st4(&s_b[sb_idx(8, ky, k)], 0.5f * (u0.y + w0.y), -0.5f * (u0.x - w0.x), 0.5f * (u1.y + w1.y),
-            -0.5f * (u1.x - w1.x));
-        st4(&s_b[sb_idx(0, ky, k)], 0.5f * (u0.x + w0.x), 0.5f * (u0.y - w0.y), 0.5f * (u1.x + w1.x),
-            0.5f * (u1.y - w1.y));
+        st4(&s_b[sb_idx(pA, ky, k)], HA[k].x, HA[k].y, HA[k + 1].x, HA[k + 1].y);
+        st4(&s_b[sb_idx(pB, ky, k)], HB[k].x, HB[k].y, HB[k + 1].x, HB[k + 1].y);
       }
-    }
-    wave_lds_sync();
-    // issued here so that their latency overlaps the rest of the flow: this
-    // row's smoothed autocorrelation (stage-C lane (hC, ixC) owns the
-    // candidates iy = hC + 3j; rows past the grid read the last one) and the
-    // delayed input sample
-    float rprev[NC_IT];
-    float idel = 0.f;
-    if (MODE != 2) {
-      const float* rp = a.rsm + pix * nv;
-      const int off0 = hC * nvx + ixC, offl = (nvy - 1) * nvx + ixC;
+      wave_lds_sync();
+      if (r == 0) {
+        // every read of plane 0 precedes every write to it (one wavefront,
+        // program order)
+        float2 w[MZ];
 #pragma unroll
-      for (int j = 0; j < NC_IT; ++j) rprev[j] = rp[(unsigned)min(off0 + 3 * j * nvx, offl)];
-    }
-    {
-      const int xs = x - a.dx, ys = y - a.dy;
-      if (ring_delayed != nullptr && xs >= 0 && ys >= 0) idel = ring_delayed[(size_t)ys * a.W + xs];
-    }
-    // next row's state and row-spectrum samples (see the pipeline note);
-    // issued after the loads above, which stage C waits for (vector memory
-    // completes in order)
-    if (y + 1 < y1) {
-      if (RING) {
-        const float2* src = a.st + (pix + a.W) * NCOL * MZ;
+        for (int k = 0; k < MZ; ++k) w[k] = ld2(&s_b[sb_idx(0, (MY - ky) & 15, (MZ - k) & 7)]);
 #pragma unroll
-        for (int m = 1; m < MZ; ++m) {
-          const int s = (slot0 - m) & 7;
-          RA[m] = ld2_stream(&src[s * NCOL + pA * MY + ky]);
-          RB[m] = ld2_stream(&src[s * NCOL + pB * MY + ky]);
-        }
-      } else {
-        const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
-#pragma unroll
-        for (int j = 0; j < MZ / 2; ++j) {
-          SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
-          SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+        for (int k = 0; k < MZ; k += 2) {
+          const float2 u0 = HA[k], u1 = HA[k + 1], w0 = w[k], w1 = w[k + 1];
+          st4(&s_b[sb_idx(8, ky, k)], 0.5f * (u0.y + w0.y), -0.5f * (u0.x - w0.x), 0.5f * (u1.y + w1.y),
+              -0.5f * (u1.x - w1.x));
+          st4(&s_b[sb_idx(0, ky, k)], 0.5f * (u0.x + w0.x), 0.5f * (u0.y - w0.y), 0.5f * (u1.x + w1.x),
+              0.5f * (u1.y - w1.y));
         }
       }
-      nA = rsA[(size_t)(y + 1) * rstride];
-      nB = rsB[(size_t)(y + 1) * rstride];
-      if (MODE != 5 && y + 1 >= MY) {
-        oA = rsA[(size_t)(y + 1 - MY) * rstride];
-        oB = rsB[(size_t)(y + 1 - MY) * rstride];
+      wave_lds_sync();
+      // issued here so that their latency overlaps the rest of the flow: this
+      // row's smoothed autocorrelation (stage-C lane (hC, ixC) owns the
+      // candidates iy = hC + 3j; rows past the grid read the last one) and the
+      // delayed input sample
+      float idel = 0.f;
+      if (MODE != 2 && F == 0) {
+        const float* rp = a.rsm + pix * nv;
+        const int off0 = hC * nvx + ixC, offl = (nvy - 1) * nvx + ixC;
+#pragma unroll
+        for (int j = 0; j < NC_IT; ++j) rprev[j] = rp[(unsigned)min(off0 + 3 * j * nvx, offl)];
       }
-    }
-
-    // ---- Hann along kx, power spectrum, stage A: Q(kx, ky) = sum_kz P w_z^kz.
-    // Planes -1 and 9 are the conjugate mirrors of planes 1 and 7:
-    // S(-1, ky, kz) = conj S(1, -ky, -kz), S(9, ky, kz) = conj S(7, -ky, -kz).
-    float2 QA, QB, Q8 = f2(0.f, 0.f);
-    float PA[MZ], PB[MZ], P8[MZ];
-#pragma unroll
-    for (int k = 0; k < MZ; ++k) P8[k] = 0.f;
-    if (r == 0) {
-      QA = hann_x_power<1, false>(s_b, ky, 0, HA, PA);
-      Q8 = hann_x_power<2, false>(s_b, ky, 8, HA, P8);
-    } else {
-      QA = hann_x_power<0, false>(s_b, ky, pA, HA, PA);
-    }
-    QB = hann_x_power<0, false>(s_b, ky, pB, HB, PB);
-    if (MODE == 1 || MODE == 2) {
-      // learned-model input: x = ln(P + eps) - mean over all Mx*My*Mz bins,
-      // eps = 1e-6 max P; stored for kx = 0..8 ([kx][ky][kz], BF16); bins
-      // with kx = 1..7 stand for their conjugate partner too (weight 2)
-      float mx = 0.f;
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) mx = fmaxf(mx, fmaxf(PA[k], fmaxf(PB[k], r == 0 ? P8[k] : 0.f)));
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-      const float eps = fmaxf(1e-6f * mx, 1e-30f);
-      float sum = 0.f;
-#pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        PA[k] = __logf(PA[k] + eps);
-        PB[k] = __logf(PB[k] + eps);
-        P8[k] = (r == 0) ? __logf(P8[k] + eps) : 0.f;
-        sum += (r == 0 ? 1.f : 2.f) * PA[k] + 2.f * PB[k] + P8[k];
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-      const float mean = sum * (1.0f / (MX * MY * MZ));
-      unsigned short* fp = a.feat + pix * (NXH * MY * MZ);
-      auto put8 = [&](int kx, const float* L) {
-        uint4 u;
-        u.x = pack_bf16x2(L[0] - mean, L[1] - mean);
-        u.y = pack_bf16x2(L[2] - mean, L[3] - mean);
-        u.z = pack_bf16x2(L[4] - mean, L[5] - mean);
-        u.w = pack_bf16x2(L[6] - mean, L[7] - mean);
-        // streamed: read once, by the network's first layer after the frame
-        __builtin_nontemporal_store(v4u{u.x, u.y, u.z, u.w}, reinterpret_cast<v4u*>(fp + (kx * MY + ky) * MZ));
-      };
-      put8(pA, PA);
-      put8(pB, PB);
-      if (r == 0) put8(8, P8);
-    }
-    // even/odd split in ky for stage B: slot 0 = Q(0), slots 1..7 = Q(k)+Q(-k),
-    // slot 8 = Q(8), slots 9..15 = Q(16-j) - Q(j-16)... stored by the lane of
-    // ky = j as Q(-ky') - Q(ky') with ky' = 16 - j
-    const float2 mA = row_neg(QA), mB = row_neg(QB), m8 = row_neg(Q8);
-    wave_lds_sync();                     // Hann-x reads of s_b are done (s_q aliases it)
-    {
-      auto put = [&](int kx, float2 q, float2 m) {
-        float2 v;
-        if (ky == 0 || ky == 8) v = q;
-        else if (ky < 8) v = f2(q.x + m.x, q.y + m.y);
-        else v = f2(m.x - q.x, m.y - q.y);
-        st2(&s_q[kx * MY + ky], v);
-      };
-      put(pA, QA, mA);
-      put(pB, QB, mB);
-      if (r == 0) put(8, Q8, m8);
-    }
-    wave_lds_sync();
-
-    // ---- stage B: T(kx, l_y) = Q0 + Q8 cos(pi l) + sum_k A_k cos + j B_k sin
-    if (actB) {
-      float cB[7], sB[7], c8B;
       {
-        const lds_float* tb = (const lds_float*)(s_tab) + iyB * 16;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) { cB[k] = tb[k]; sB[k] = tb[7 + k]; }
-        c8B = tb[14];
+        const int xs = x - a.dx, ys = y - a.dy;
+        if (rdel != nullptr && xs >= 0 && ys >= 0) idel = rdel[(size_t)ys * a.W + xs];
       }
+      // next row's state and row-spectrum samples (see the pipeline note);
+      // issued after the loads above, which stage C waits for (vector memory
+      // completes in order)
+      if (y + 1 < y1) {
+        if (F > 0) {
+        } else if (RING) {
+          const float2* src = a.st + (pix + a.W) * NCOL * MZ;
+#pragma unroll
+          for (int m = 1; m < MZ; ++m) {
+            const int s = (slot0 - m) & 7;
+            RA[m] = ld2_stream(&src[s * NCOL + pA * MY + ky]);
+            RB[m] = ld2_stream(&src[s * NCOL + pB * MY + ky]);
+          }
+        } else {
+          const float4* src = reinterpret_cast<const float4*>(a.st + (pix + a.W) * NCOL * MZ);
+#pragma unroll
+          for (int j = 0; j < MZ / 2; ++j) {
+            SnA[j] = ld_stream(&src[j * NCOL + pA * MY + ky]);
+            SnB[j] = ld_stream(&src[j * NCOL + pB * MY + ky]);
+          }
+        }
+        cnA = frA[(size_t)(y + 1) * rstride];
+        cnB = frB[(size_t)(y + 1) * rstride];
+        if (MODE != 5 && y + 1 >= MY) {
+          coA = frA[(size_t)(y + 1 - MY) * rstride];
+          coB = frB[(size_t)(y + 1 - MY) * rstride];
+        }
+      }
+
+      // ---- Hann along kx, power spectrum, stage A: Q(kx, ky) = sum_kz P w_z^kz.
+      // Planes -1 and 9 are the conjugate mirrors of planes 1 and 7:
+      // S(-1, ky, kz) = conj S(1, -ky, -kz), S(9, ky, kz) = conj S(7, -ky, -kz).
+      float2 QA, QB, Q8 = f2(0.f, 0.f);
+      float PA[MZ], PB[MZ], P8[MZ];
+#pragma unroll
+      for (int k = 0; k < MZ; ++k) P8[k] = 0.f;
+      if (r == 0) {
+        QA = hann_x_power<1, false>(s_b, ky, 0, HA, PA);
+        Q8 = hann_x_power<2, false>(s_b, ky, 8, HA, P8);
+      } else {
+        QA = hann_x_power<0, false>(s_b, ky, pA, HA, PA);
+      }
+      QB = hann_x_power<0, false>(s_b, ky, pB, HB, PB);
+      if (MODE == 1 || MODE == 2) {
+        // learned-model input: x = ln(P + eps) - mean over all Mx*My*Mz bins,
+        // eps = 1e-6 max P; stored for kx = 0..8 ([kx][ky][kz], BF16); bins
+        // with kx = 1..7 stand for their conjugate partner too (weight 2)
+        float mx = 0.f;
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) mx = fmaxf(mx, fmaxf(PA[k], fmaxf(PB[k], r == 0 ? P8[k] : 0.f)));
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
+        const float eps = fmaxf(1e-6f * mx, 1e-30f);
+        float sum = 0.f;
+#pragma unroll
+        for (int k = 0; k < MZ; ++k) {
+          PA[k] = __logf(PA[k] + eps);
+          PB[k] = __logf(PB[k] + eps);
+          P8[k] = (r == 0) ? __logf(P8[k] + eps) : 0.f;
+          sum += (r == 0 ? 1.f : 2.f) * PA[k] + 2.f * PB[k] + P8[k];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        const float mean = sum * (1.0f / (MX * MY * MZ));
+        unsigned short* fp = a.feat + pix * (NXH * MY * MZ);
+        auto put8 = [&](int kx, const float* L) {
+          uint4 u;
+          u.x = pack_bf16x2(L[0] - mean, L[1] - mean);
+          u.y = pack_bf16x2(L[2] - mean, L[3] - mean);
+          u.z = pack_bf16x2(L[4] - mean, L[5] - mean);
+          u.w = pack_bf16x2(L[6] - mean, L[7] - mean);
+          // streamed: read once, by the network's first layer after the frame
+          __builtin_nontemporal_store(v4u{u.x, u.y, u.z, u.w}, reinterpret_cast<v4u*>(fp + (kx * MY + ky) * MZ));
+        };
+        put8(pA, PA);
+        put8(pB, PB);
+        if (r == 0) put8(8, P8);
+      }
+      // even/odd split in ky for stage B: slot 0 = Q(0), slots 1..7 = Q(k)+Q(-k),
+      // slot 8 = Q(8), slots 9..15 = Q(16-j) - Q(j-16)... stored by the lane of
+      // ky = j as Q(-ky') - Q(ky') with ky' = 16 - j
+      const float2 mA = row_neg(QA), mB = row_neg(QB), m8 = row_neg(Q8);
+      wave_lds_sync();                     // Hann-x reads of s_b are done (s_q aliases it)
+      {
+        auto put = [&](int kx, float2 q, float2 m) {
+          float2 v;
+          if (ky == 0 || ky == 8) v = q;
+          else if (ky < 8) v = f2(q.x + m.x, q.y + m.y);
+          else v = f2(m.x - q.x, m.y - q.y);
+          st2(&s_q[kx * MY + ky], v);
+        };
+        put(pA, QA, mA);
+        put(pB, QB, mB);
+        if (r == 0) put(8, Q8, m8);
+      }
+      wave_lds_sync();
+
+      // ---- stage B: T(kx, l_y) = Q0 + Q8 cos(pi l) + sum_k A_k cos + j B_k sin
+      if (actB) {
+        float cB[7], sB[7], c8B;
+        {
+          const lds_float* tb = (const lds_float*)(s_tab) + iyB * 16;
+#pragma unroll
+          for (int k = 0; k < 7; ++k) { cB[k] = tb[k]; sB[k] = tb[7 + k]; }
+          c8B = tb[14];
+        }
 #pragma unroll 1
-      for (int j = 0; j < 3; ++j) {
-        const int kx = 3 * gB + j;
-        const lds_v2* q = s_q + kx * MY;
-        float tx = q[0].x + c8B * q[8].x, ty = q[0].y + c8B * q[8].y;
+        for (int j = 0; j < 3; ++j) {
+          const int kx = 3 * gB + j;
+          const lds_v2* q = s_q + kx * MY;
+          float tx = q[0].x + c8B * q[8].x, ty = q[0].y + c8B * q[8].y;
 #pragma unroll
-        for (int k = 1; k < 8; ++k) {
-          const v2f A = q[k], Bv = q[16 - k];
-          tx += cB[k - 1] * A.x - sB[k - 1] * Bv.y;
-          ty += cB[k - 1] * A.y + sB[k - 1] * Bv.x;
-        }
-        st2(&s_t[kx * NV1_MAX + iyB], f2(tx, ty));
-      }
-    }
-    wave_lds_sync();
-
-    // ---- stage C: R = T0 + T8 cos(pi l_x) + sum_kx 2 Re[T e^{+j phi}],
-    // smoothing and argmax
-    float bv = -INFINITY;
-    int bi = 0x7fffffff;
-    float smv[MODE == 3 ? NC_IT : 1];    // mode 3: this lane's smoothed R, for the peak's neighbours
-#pragma unroll
-    for (int j = 0; j < (MODE == 3 ? NC_IT : 1); ++j) smv[j] = 0.f;
-    if (actC) {
-      float cC[7], sC[7], c8C;
-      {
-        const lds_float* tc = (const lds_float*)(s_tab) + (4 * NV1_MAX + 4 * ixC) * 4;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) { cC[k] = tc[k]; sC[k] = tc[7 + k]; }
-        c8C = tc[14];
-      }
-#pragma unroll
-      for (int j = 0; j < NC_IT; ++j) {
-        const int iy = hC + 3 * j;
-        if (iy < nvy) {
-          float rv = s_t[0 * NV1_MAX + iy].x + c8C * s_t[8 * NV1_MAX + iy].x;
-#pragma unroll
-          for (int kx = 1; kx < 8; ++kx) {
-            const v2f t = s_t[kx * NV1_MAX + iy];
-            rv += cC[kx - 1] * t.x - sC[kx - 1] * t.y;
+          for (int k = 1; k < 8; ++k) {
+            const v2f A = q[k], Bv = q[16 - k];
+            tx += cB[k - 1] * A.x - sB[k - 1] * Bv.y;
+            ty += cB[k - 1] * A.y + sB[k - 1] * Bv.x;
           }
-          const int w = iy * nvx + ixC;
-          float sm = rv;                   // learned mode: instantaneous R (no smoother state)
-          if (MODE != 2) {
-            sm = (1.f - a.alpha) * rv + a.alpha * rprev[j];
-            a.rsm[pix * nv + w] = sm;
-          }
-          if (MODE == 3) smv[j] = sm;
-          amax_merge(bv, bi, sm, w);
+          st2(&s_t[kx * NV1_MAX + iyB], f2(tx, ty));
         }
-        __builtin_amdgcn_sched_barrier(0);   // keep one iteration's LDS reads in flight at a time
       }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const float v2 = __shfl_xor(bv, off, 64);
-      const int i2 = __shfl_xor(bi, off, 64);
-      amax_merge(bv, bi, v2, i2);
-    }
-    const int istar = (bi < nv) ? bi : 0;
-    if (MODE == 2 && lane == 0) a.fidx[pix] = istar;
+      wave_lds_sync();
 
-    // ---- mode 3: the peak refined between grid points; R at (ix, iy) is held
-    // by lane (iy mod 3) nvx + ix in its slot iy / 3
-    float2 vref = f2(0.f, 0.f);
-    if (MODE == 3) {
-      const int best = __builtin_amdgcn_readfirstlane(istar);
-      auto rv = [&](int w) -> float {
-        const int iyn = w / nvx, ixn = w - iyn * nvx;
-        const int jn = iyn / 3, src = (iyn - 3 * jn) * nvx + ixn;
-        float v = 0.f;
+      // ---- stage C: R = T0 + T8 cos(pi l_x) + sum_kx 2 Re[T e^{+j phi}],
+      // smoothing and argmax
+      float bv = -INFINITY;
+      int bi = 0x7fffffff;
+      float smv[MODE == 3 ? NC_IT : 1];    // mode 3: this lane's smoothed R, for the peak's neighbours
 #pragma unroll
-        for (int j = 0; j < (MODE == 3 ? NC_IT : 1); ++j)
-          if (j == jn) v = smv[j];
-        return __shfl(v, src, 64);
-      };
-      const float rbest = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bv)));
-      vref = refine_peak(a.gx, a.gy, nvx, nvy, best, rbest, rv);
-    }
+      for (int j = 0; j < (MODE == 3 ? NC_IT : 1); ++j) smv[j] = 0.f;
+      if (actC) {
+        float cC[7], sC[7], c8C;
+        {
+          const lds_float* tc = (const lds_float*)(s_tab) + (4 * NV1_MAX + 4 * ixC) * 4;
+#pragma unroll
+          for (int k = 0; k < 7; ++k) { cC[k] = tc[k]; sC[k] = tc[7 + k]; }
+          c8C = tc[14];
+        }
+#pragma unroll
+        for (int j = 0; j < NC_IT; ++j) {
+          const int iy = hC + 3 * j;
+          if (iy < nvy) {
+            float rv = s_t[0 * NV1_MAX + iy].x + c8C * s_t[8 * NV1_MAX + iy].x;
+#pragma unroll
+            for (int kx = 1; kx < 8; ++kx) {
+              const v2f t = s_t[kx * NV1_MAX + iy];
+              rv += cC[kx - 1] * t.x - sC[kx - 1] * t.y;
+            }
+            const int w = iy * nvx + ixC;
+            float sm = rv;                   // learned mode: instantaneous R (no smoother state)
+            if (MODE != 2) {
+              sm = (1.f - a.alpha) * rv + a.alpha * rprev[j];
+              if (LAST) a.rsm[pix * nv + w] = sm;
+              else rprev[j] = sm;          // the pair's next frame smooths on from here
+            }
+            if (MODE == 3) smv[j] = sm;
+            amax_merge(bv, bi, sm, w);
+          }
+          __builtin_amdgcn_sched_barrier(0);   // keep one iteration's LDS reads in flight at a time
+        }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const float v2 = __shfl_xor(bv, off, 64);
+        const int i2 = __shfl_xor(bi, off, 64);
+        amax_merge(bv, bi, v2, i2);
+      }
+      const int istar = (bi < nv) ? bi : 0;
+      if (MODE == 2 && lane == 0) a.fidx[pix] = istar;
 
-    // ---- background estimate with the chosen velocity's coefficients (the
-    // posterior state is still in registers)
-    const int hsel = __builtin_amdgcn_readfirstlane((a.vmode == 2) ? nv : istar);
-    float acc = 0.f;
-    if (MODE == 3) {
-      if (kyc >= -a.by && kyc <= a.by) {
-        if (pA <= a.bx) acc = pef_plane16(XA, pA, kyc, vref.x, vref.y, a.dx, a.dy, a.dt);
-        if (pB <= a.bx) acc += pef_plane16(XB, pB, kyc, vref.x, vref.y, a.dx, a.dy, a.dt);
-      }
-    } else if (lattice) {
-      // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
-      const int nq = a.latq[hsel];
-      const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
-      const int qm = a.lat_q - 1;
-      const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
-      const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
-      const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
-      float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
+      // ---- mode 3: the peak refined between grid points; R at (ix, iy) is held
+      // by lane (iy mod 3) nvx + ix in its slot iy / 3
+      float2 vref = f2(0.f, 0.f);
+      if (MODE == 3) {
+        const int best = __builtin_amdgcn_readfirstlane(istar);
+        auto rv = [&](int w) -> float {
+          const int iyn = w / nvx, ixn = w - iyn * nvx;
+          const int jn = iyn / 3, src = (iyn - 3 * jn) * nvx + ixn;
+          float v = 0.f;
 #pragma unroll
-      for (int k = 0; k < MZ; ++k) {
-        const v2f g = gA[k], h = gB[k];
-        sA.x += g.x * XA[k].x - g.y * XA[k].y;
-        sA.y += g.x * XA[k].y + g.y * XA[k].x;
-        sB.x += h.x * XB[k].x - h.y * XB[k].y;
-        sB.y += h.x * XB[k].y + h.y * XB[k].x;
+          for (int j = 0; j < (MODE == 3 ? NC_IT : 1); ++j)
+            if (j == jn) v = smv[j];
+          return __shfl(v, src, 64);
+        };
+        const float rbest = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(bv)));
+        vref = refine_peak(a.gx, a.gy, nvx, nvy, best, rbest, rv);
       }
-      const float2 EA = ld2(e), EB = ld2(e + 4 * 17);
-      acc = (EA.x * sA.x - EA.y * sA.y) + (EB.x * sB.x - EB.y * sB.y);
-    } else if (kyc >= -a.by && kyc <= a.by) {
-      const size_t row = (size_t)hsel * (a.bx + 1);
-      if (pA <= a.bx) {
-        const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+
+      // ---- background estimate with the chosen velocity's coefficients (the
+      // posterior state is still in registers)
+      const int hsel = __builtin_amdgcn_readfirstlane((a.vmode == 2) ? nv : istar);
+      float acc = 0.f;
+      if (MODE == 3) {
+        if (kyc >= -a.by && kyc <= a.by) {
+          if (pA <= a.bx) acc = pef_plane16(XA, pA, kyc, vref.x, vref.y, a.dx, a.dy, a.dt);
+          if (pB <= a.bx) acc += pef_plane16(XB, pB, kyc, vref.x, vref.y, a.dx, a.dy, a.dt);
+        }
+      } else if (lattice) {
+        // coefficient = E(kx, ky) G[(nx kx + ny ky) mod Q][kz]; sum_kz G X first
+        const int nq = a.latq[hsel];
+        const int nxv = nq >> 16, nyv = (int)(short)(nq & 0xffff);
+        const int qm = a.lat_q - 1;
+        const lds_v2* gA = s_g + ((nxv * pA + nyv * kyc) & qm) * MZ;
+        const lds_v2* gB = s_g + ((nxv * pB + nyv * kyc) & qm) * MZ;
+        const lds_v2* e = s_g + LATQ_MAX * MZ + pA * 17 + kyc + 8;   // plane pB = pA + 4
+        float2 sA = f2(0.f, 0.f), sB = f2(0.f, 0.f);
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
-      }
-      if (pB <= a.bx) {
-        const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
+        for (int k = 0; k < MZ; ++k) {
+          const v2f g = gA[k], h = gB[k];
+          sA.x += g.x * XA[k].x - g.y * XA[k].y;
+          sA.y += g.x * XA[k].y + g.y * XA[k].x;
+          sB.x += h.x * XB[k].x - h.y * XB[k].y;
+          sB.y += h.x * XB[k].y + h.y * XB[k].x;
+        }
+        const float2 EA = ld2(e), EB = ld2(e + 4 * 17);
+        acc = (EA.x * sA.x - EA.y * sA.y) + (EB.x * sB.x - EB.y * sB.y);
+      } else if (kyc >= -a.by && kyc <= a.by) {
+        const size_t row = (size_t)hsel * (a.bx + 1);
+        if (pA <= a.bx) {
+          const float2* h = a.htab + ((row + pA) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-        for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
-      }
-    }
+          for (int k = 0; k < MZ; ++k) acc += h[k].x * XA[k].x - h[k].y * XA[k].y;
+        }
+        if (pB <= a.bx) {
+          const float2* h = a.htab + ((row + pB) * (2 * a.by + 1) + (kyc + a.by)) * MZ;
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) {
-      if (!isfinite(idel)) idel = 0.f;
-      a.out[pix] = idel - acc;
-      if (a.vmode == 2) {
-        a.vxy[pix] = make_float2(a.fvx, a.fvy);
-        a.vidx[pix] = -1;
-      } else {
-        a.vxy[pix] = (MODE == 3) ? vref : make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
-        a.vidx[pix] = istar;
+          for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
+        }
       }
-    }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+      if (lane == 0 && !LAST) {
+        if (!isfinite(idel)) idel = 0.f;
+        a.out_first[pix] = idel - acc;   // the pair's first frame: its output only
+      } else if (lane == 0) {
+        if (!isfinite(idel)) idel = 0.f;
+        a.out[pix] = idel - acc;
+        if (a.vmode == 2) {
+          a.vxy[pix] = make_float2(a.fvx, a.fvy);
+          a.vidx[pix] = -1;
+        } else {
+          a.vxy[pix] = (MODE == 3) ? vref : make_float2(a.gx[istar % nvx], a.gy[istar / nvx]);
+          a.vidx[pix] = istar;
+        }
+      }
+    };
+    frame(std::integral_constant<int, 0>{});
+    if constexpr (MODE == 6) frame(std::integral_constant<int, 1>{});
   }
 }
 

@@ -59,6 +59,7 @@ hipError_t launch_pixel16(const PixArgs& a, int mode, hipStream_t s) {
   else if (mode == 3) hipLaunchKernelGGL(p16::k_pixel16<3>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else if (mode == 4) hipLaunchKernelGGL(p16::k_pixel16<4>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else if (mode == 5) hipLaunchKernelGGL(p16::k_pixel16<5>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
+  else if (mode == 6) hipLaunchKernelGGL(p16::k_pixel16<6>, dim3(xblocks * yblocks), dim3(256), 0, s, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

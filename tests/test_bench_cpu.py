@@ -44,6 +44,14 @@ def test_committed_traffic_summaries_match_the_sources():
         assert bench.measured_traffic("k_pixel16", wl) is not None, wl
     assert bench.measured_traffic("k_pixel16<4>", "640x512", "ring") is not None
     assert bench.measured_traffic("k_pixel16<5>", "640x512", "direct") is not None
+    assert bench.measured_traffic("k_pixel16<6>", "640x512", "pairs") is not None
+
+
+def test_pair_bytes_model():
+    """Frame pairs move the state and smoothed R once per two frames."""
+    single = bench.algorithmic_bytes_per_pixel_frame((16, 16, 8), 289)
+    pair = bench.pair_bytes_per_pixel_frame((16, 16, 8), 289)
+    assert pair == (single - 24) / 2 + 18
 
 
 def test_more_than_one_gpu_is_refused():
