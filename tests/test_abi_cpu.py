@@ -90,6 +90,7 @@ def test_null_context_calls(L):
     assert L.rmdf_output(None, None) == -1
     assert L.rmdf_velocity(None, None, None) == -1
     assert L.rmdf_spectrum_noalloc(None, 0, None, None, None) == -1
+    assert L.rmdf_push_frames(None, 2, None, None) == -1
     assert L.rmdf_destroy(None) == 0
 
 
