@@ -278,7 +278,12 @@ static __device__ __forceinline__ void dft8p_scaled(const float2* x, float2* X) 
 // posterior in exact arithmetic), halving the state traffic; 5 as 4 with the
 // column DFT taken directly as well (sum over the window's My row spectra,
 // kept in LDS), with the row pass also direct: no recursion on any axis, the
-// non-recursive local spectrum as a comparison point.
+// non-recursive local spectrum as a comparison point; 6 as 0 for two frames
+// per pass (frame pairs): the row's work runs for the pair's first frame
+// (row spectra a.rs, output to a.out_first) and then for its second (a.rs2,
+// the context's outputs), the second starting from the first's posterior
+// and smoothed R held in registers, so that the state and the smoothed R
+// are read and written once per pair.
 template <int MODE>
 static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const float* ring_delayed, int xb, int yb, char* smem) {
   lds_v2* s_all = (lds_v2*)(smem);
