@@ -153,7 +153,9 @@ struct Shape {
   static constexpr int A_ELEMS = PPB * NCOL * MZ;           // Hann staging (float2)
   static constexpr int QT_ELEMS = PPB * NXH * (MY + NVY_MAX);
   static constexpr int U_ELEMS = A_ELEMS > QT_ELEMS ? A_ELEMS : QT_ELEMS;
-  static constexpr size_t SMEM = sizeof(float2) * (U_ELEMS + A_ELEMS + 2 * MZ + MY) + (sizeof(float) + sizeof(int)) * 256;
+  static constexpr int TAB_ELEMS = NVY_MAX * MY + NVX_MAX * NXH;  // tau_y and tau_x, staged per tile
+  static constexpr size_t SMEM = sizeof(float2) * (U_ELEMS + A_ELEMS + 2 * MZ + MY + TAB_ELEMS) +
+                                 (sizeof(float) + sizeof(int)) * 256;
 };
 
 // (value, index) argmax with the first (lowest-index) maximum winning.
@@ -195,7 +197,9 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
   float2* s_twz = s_b + SH::A_ELEMS;
   float2* s_twA = s_twz + MZ;
   float2* s_twy = s_twA + MZ;
-  float* s_rv = reinterpret_cast<float*>(s_twy + MY);
+  float2* s_tauy = s_twy + MY;                   // [nvy][MY]
+  float2* s_taux = s_tauy + NVY_MAX * MY;        // [nvx][NXH]
+  float* s_rv = reinterpret_cast<float*>(s_taux + NVX_MAX * NXH);
   int* s_ri = reinterpret_cast<int*>(s_rv + 256);
 
   const int tid = threadIdx.x;
@@ -209,6 +213,10 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
 
   for (int i = tid; i < MZ; i += 256) { s_twz[i] = a.twz[i]; s_twA[i] = a.twA[i]; }
   for (int i = tid; i < MY; i += 256) s_twy[i] = a.twy[i];
+  // the stage B and C weight tables too: read there once per candidate and
+  // row, from LDS they add no global-load latency to every row's flow
+  for (int i = tid; i < a.nvy * MY; i += 256) s_tauy[i] = a.tauy[i];
+  for (int i = tid; i < a.nvx * NXH; i += 256) s_taux[i] = a.taux[i];
   __syncthreads();
 
   float2* s_a = s_u;                                   // [PPB][NCOL][MZ]
@@ -375,7 +383,7 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
     for (int w = c; w < NXH * nvy; w += NCOLP) {
       const int kx = w / nvy, iy = w % nvy;
       const float2* Q = s_q + (ps * NXH + kx) * MY;
-      const float2* ty = a.tauy + iy * MY;
+      const float2* ty = s_tauy + iy * MY;
       float2 t = make_float2(0.f, 0.f);
 #pragma unroll
       for (int k = 0; k < MY; ++k) t = cadd(t, cmul(Q[k], ty[k]));
@@ -389,7 +397,7 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
     int bi = 0x7fffffff;
     for (int w = c; w < nv; w += NCOLP) {
       const int ix = w % nvx, iy = w / nvx;
-      const float2* tx = a.taux + ix * NXH;
+      const float2* tx = s_taux + ix * NXH;
       float r = 0.f;
 #pragma unroll
       for (int kx = 0; kx < NXH; ++kx) {
