@@ -425,8 +425,9 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
   if ((e = hipMalloc(&b->d_pix, sizeof(BatchPixDesc) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "descriptors");
   if ((e = hipMalloc(&b->d_t, sizeof(long long) * n)) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
   if ((e = hipMalloc(&b->d_queue, NKIND * sizeof(unsigned int))) != hipSuccess) return bail(RMDF_E_NOMEM, "counters");
-  hipMemcpy(b->d_row, rd.data(), sizeof(RowDesc) * n, hipMemcpyHostToDevice);
-  hipMemcpy(b->d_t, b->t.data(), sizeof(long long) * n, hipMemcpyHostToDevice);
+  if ((e = hipMemcpy(b->d_row, rd.data(), sizeof(RowDesc) * n, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(b->d_t, b->t.data(), sizeof(long long) * n, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(RMDF_E_DEVICE, std::string("descriptor upload: ") + hipGetErrorString(e));
   hipLaunchKernelGGL(k_batch_arm, dim3(1), dim3(64), 0, b->stream, BatchState{b->d_t, b->d_queue});
   if ((e = rebuild(b)) != hipSuccess) return bail(RMDF_E_DEVICE, std::string("graph: ") + hipGetErrorString(e));
   if ((e = hipStreamSynchronize(b->stream)) != hipSuccess) return bail(RMDF_E_DEVICE, "sync");

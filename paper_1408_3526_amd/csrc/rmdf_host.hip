@@ -489,10 +489,9 @@ static void timed_end(rmdf_ctx* c, EventPair* ev) {
   c->events.push_back(*ev);
 }
 
-// The learned network on n feature rows: two MFMA GEMM layers (bias and ReLU
-// fused, BF16 outputs) into the context's hidden-layer buffers, then the head.
-// The network on n feature rows in one kernel; list != nullptr also collects
-// the rows whose confidence clears the context's threshold.
+// The learned network on n feature rows in one kernel (three layers, BF16
+// MFMA with FP32 accumulation); list != nullptr also collects the rows whose
+// confidence clears the context's threshold.
 static hipError_t run_network(rmdf_ctx* c, const unsigned short* feat, int n, float* vc, int* list) {
   return rmdf::launch_mlp_infer(feat, n, c->w1, c->b1, c->w2, c->b2, c->w3, c->b3, vc, c->conf, list, c->stream);
 }
@@ -665,6 +664,18 @@ rmdf_status rmdf_spectrum(rmdf_ctx* c, int npix, const int* xs, const int* ys, f
   }
   hipError_t e;
   if (npix > c->xy_cap) {
+    // the previous buffer is idle (every call ends with a stream synchronisation)
+    if (c->xy_scratch) {
+      for (auto it = c->allocs.begin(); it != c->allocs.end(); ++it)
+        if (*it == static_cast<void*>(c->xy_scratch)) {
+          c->allocs.erase(it);
+          break;
+        }
+      hipFree(c->xy_scratch);
+      c->bytes -= 2 * (size_t)c->xy_cap * sizeof(int);
+      c->xy_scratch = nullptr;
+      c->xy_cap = 0;
+    }
     if ((e = dalloc(c, &c->xy_scratch, 2 * (size_t)npix)) != hipSuccess) return hip_fail(c, e, "scratch");
     c->xy_cap = npix;
   }

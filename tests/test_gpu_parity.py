@@ -392,6 +392,27 @@ def test_deterministic():
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_spectrum_anchor_buffer_grows_and_is_replaced():
+    # the anchor staging buffer grows with the largest request; the old buffer
+    # is released, so the context's device footprint tracks the largest call
+    b = _binding()
+    g = scenes.grid(-1, 1, 1.0)
+    sc = scenes.translate_scene(5, H=24, W=20, T=5, v=(1, 0))
+    f = b.Filter(24, 20, 8, 8, 4, g, g)
+    for fr in sc.frames:
+        f.push_frame(torch.from_numpy(fr).cuda())
+    base = f.device_bytes()
+    xs = np.arange(24 * 20) % 20
+    ys = np.arange(24 * 20) // 20
+    subs = {n: f.spectrum(xs[:n], ys[:n]).cpu().numpy() for n in (1, 7, 100, 3, 480, 5)}
+    # one buffer of 480 (x, y) pairs remains, not 1 + 7 + 100 + 480
+    assert f.device_bytes() == base + 2 * 480 * 4
+    full = f.spectrum(xs, ys).cpu().numpy()
+    for n, sub in subs.items():
+        assert np.array_equal(sub, full[:n]), n
+    f.close()
+
+
 def test_state_errors():
     b = _binding()
     g = scenes.grid(-1, 1, 1.0)
