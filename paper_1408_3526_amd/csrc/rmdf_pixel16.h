@@ -16,8 +16,8 @@
 //   stage B (ky -> l_y)       lanes = (kx group, l_y); even/odd split in ky
 //   stage C (kx -> l_x)       lanes = (l_y group, l_x); smoothing; argmax
 //   background estimate       lanes' own columns x coefficient table
-// Trigonometric weights of stages B and C stay in registers for the whole
-// kernel.
+// Trigonometric weights of stages B and C are staged in LDS once per tile
+// and read into registers for each row's stage.
 #pragma once
 #include <hip/hip_runtime.h>
 
