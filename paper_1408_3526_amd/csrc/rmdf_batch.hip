@@ -1,15 +1,19 @@
 // rmdf_batch.hip - many independent sensor streams (uneven frame sizes and
-// windows) advanced one frame per step by two kernels captured in a hipGraph:
-//   k_row_batch        row sliding DFT of every stream (one block per
-//                      (stream, row, chunk)); reads each stream's raw frame from
-//                      its delay-ring slot, non-finite samples read as 0
-//   k_batch_p16        persistent workgroups pull (stream, tile) items of the
-//   k_batch_generic    16x16x8 wave-per-anchor streams (resp. all other
-//                      windows) from an atomic queue ordered by decreasing
-//                      cost and run that stream's per-pixel tile; one kernel
-//                      per tile family, so each gets its own register budget
-//   k_batch_advance    advances every stream's frame counter and re-arms the
-//                      queues for the next step
+// windows) advanced one frame per step by the kernels of one hipGraph:
+//   k_row_batch          row sliding DFT of every stream (one block per
+//                        (stream, row, chunk)); reads each stream's raw frame
+//                        from its delay-ring slot, non-finite samples read as 0
+//   k_batch_tiles<KIND>  persistent workgroups pull (stream, tile) items of one
+//                        tile family (8x8x4, 9x9x5, generic 16x16x8, 16x16x8
+//                        wave-per-anchor) from an atomic queue ordered by
+//                        decreasing cost and run that stream's per-pixel tile;
+//                        one kernel per family, each with its own register
+//                        budget (the default schedule)
+//   k_batch_mixed        the alternative schedule: one persistent kernel whose
+//                        single queue interleaves the wave-per-anchor, 8x8x4
+//                        and 9x9x5 tiles
+//   k_batch_advance      advances every stream's frame counter and re-arms the
+//                        queues for the next step
 // Nothing in the graph changes between steps: frame counters live in device
 // memory and frames are written into the ring slots before each launch.
 #include <hip/hip_runtime.h>
