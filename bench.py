@@ -226,6 +226,42 @@ def batch_leg(frames_np, specs, steps, warmup, tune_iters=5):
             "autotune": report.strip().splitlines()}
 
 
+def cpu_baseline_batch(frames_np, specs, strip_rows=32, n_frames=4):
+    """The FP64 oracle on the batched workload: one full-width strip
+    (strip_rows rows plus the My - 1 rows above) of the first stream of each
+    size class over its first n_frames frames, all host cores; the aggregate
+    rate is the step's pixel count over the time the oracle would take for
+    every stream of the step at its class's rate.  A few seconds of CPU work."""
+    import numpy as np
+
+    import oracle
+    oracle.lib()
+    cores = oracle.threads()
+    per_class, seen = [], set()
+    for f, sp in zip(frames_np, specs):
+        key = (sp["H"], sp["W"], sp["M"])
+        if key in seen:
+            continue
+        seen.add(key)
+        H, W, M = sp["H"], sp["W"], sp["M"]
+        y0 = H // 2 - strip_rows // 2
+        ya = max(0, y0 - (M[1] - 1))
+        sub = np.ascontiguousarray(f[:n_frames, ya:y0 + strip_rows, :])
+        cfg = oracle.Cfg(H=sub.shape[1], W=W, Mx=M[0], My=M[1], Mz=M[2], gx=sp["gx"], gy=sp["gy"])
+        t0 = time.perf_counter()
+        oracle.run(cfg, sub)
+        dt = time.perf_counter() - t0
+        per_class.append({"stream": "%dx%d @%dx%dx%d" % (W, H, *M), "rate": n_frames * strip_rows * W / dt,
+                          "seconds": dt})
+    rate = {c["stream"]: c["rate"] for c in per_class}
+    step_s = sum(sp["H"] * sp["W"] / rate["%dx%d @%dx%dx%d" % (sp["W"], sp["H"], *sp["M"])] for sp in specs)
+    px = sum(sp["H"] * sp["W"] for sp in specs)
+    return {"value": px / step_s, "unit": "pixel-frames/s", "cores": cores, "kind": "oracle",
+            "sample": "one full-width %d-row strip (+My-1 rows above, centred) of one stream per size class, "
+                      "first %d frames; aggregate over the step's %d streams" % (strip_rows, n_frames, len(specs)),
+            "per_class": per_class}
+
+
 def batch_bench(args):
     """The batched-streams workload on its own (--batch24): one JSON line."""
     frames_np, specs = batch_inputs(args.frames or 12)
@@ -233,6 +269,8 @@ def batch_bench(args):
     res = {"metric": "batched streams: aggregate pixel-frames/s, per-step latency", "mode": "batch24",
            "n_gpus": 1, "higher_is_better": True, "dtype": "f32", "data": "synthetic"}
     res.update(r)
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline_batch(frames_np, specs)
     print(json.dumps(res), flush=True)
 
 
@@ -740,6 +778,8 @@ def main():
         del dev
         torch.cuda.empty_cache()
         res["batch24"] = batch_leg(*batch_in, steps=min(args.steps, 20), warmup=min(args.warmup, 5), tune_iters=3)
+        if not args.no_cpu_baseline:
+            res["batch24"]["cpu_baseline"] = cpu_baseline_batch(*batch_in)
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(frames, wl, g)
     print(json.dumps(res), flush=True)

@@ -65,3 +65,23 @@ def test_more_than_one_gpu_is_refused():
 def test_workloads_are_well_formed(wl):
     w = bench.WORKLOADS[wl]
     assert w["H"] >= 1 and w["W"] >= 1 and len(w["M"]) == 3
+
+
+def test_batch_cpu_baseline_aggregates_the_step(monkeypatch):
+    """The batched workload's oracle rate: one strip per size class, combined
+    as the step's pixel count over the summed per-stream times."""
+    import numpy as np
+
+    from paper_1408_3526_amd import scenes
+    g8, g16 = scenes.grid(-1, 1, 1.0), scenes.grid(-1, 1, 1.0)
+    rng = np.random.default_rng(0)
+    specs = [dict(H=20, W=24, M=(8, 8, 4), gx=g8, gy=g8), dict(H=20, W=24, M=(8, 8, 4), gx=g8, gy=g8),
+             dict(H=24, W=20, M=(16, 16, 8), gx=g16, gy=g16)]
+    frames = [rng.normal(size=(2, sp["H"], sp["W"])).astype(np.float32) for sp in specs]
+    r = bench.cpu_baseline_batch(frames, specs, strip_rows=8, n_frames=2)
+    assert r["kind"] == "oracle" and r["cores"] >= 1
+    # two size classes timed; the aggregate is px / (2 * 480 / rate8 + 480 / rate16)
+    rates = {c["stream"]: c["rate"] for c in r["per_class"]}
+    assert len(rates) == 2
+    expect = 3 * 480 / (2 * 480 / rates["24x20 @8x8x4"] + 480 / rates["20x24 @16x16x8"])
+    assert abs(r["value"] - expect) <= 1e-9 * expect
