@@ -579,7 +579,12 @@ def cpu_baseline(frames, wl, g, strip_rows=64, n_frames=6, runs=3):
     My = wl["M"][1]
     oracle.lib()
     cores = oracle.threads()
-    starts = [min(H - strip_rows, max(0, (k + 1) * H // (runs + 1) - strip_rows // 2)) for k in range(runs)]
+    whole = H <= strip_rows           # small frames: the whole workload, every frame
+    if whole:
+        strip_rows, n_frames = H, T
+        starts = [0] * runs
+    else:
+        starts = [min(H - strip_rows, max(0, (k + 1) * H // (runs + 1) - strip_rows // 2)) for k in range(runs)]
     rates = []
     for y0 in starts:
         ya = max(0, y0 - (My - 1))
@@ -608,9 +613,11 @@ def cpu_baseline(frames, wl, g, strip_rows=64, n_frames=6, runs=3):
         pass
     return {"value": value, "unit": "pixel-frames/s", "cores": cores, "kind": "oracle",
             "host": {"cpu": model, "usable_cpus": len(os.sched_getaffinity(0))},
-            "sample": "median of %d runs, each a full-width %d-row strip (+%d rows above, rows %s) of the "
-                      "workload's frames over its first %d frames; rates %s pixel-frames/s"
-                      % (runs, strip_rows, My - 1, starts, n_frames, [round(r) for r in rates]),
+            "sample": ("median of %d runs over the whole workload (%d frames of %dx%d); rates %s pixel-frames/s"
+                       % (runs, T, W, H, [round(r) for r in rates])) if whole else
+                      ("median of %d runs, each a full-width %d-row strip (+%d rows above, rows %s) of the "
+                       "workload's frames over its first %d frames; rates %s pixel-frames/s"
+                       % (runs, strip_rows, My - 1, starts, n_frames, [round(r) for r in rates])),
             "one_thread": {"value": n1 / dt1, "cores": 1,
                            "sample": "64x48 crop, 4 frames (%d pixel-frames, %.1f s)" % (n1, dt1)}}
 
