@@ -120,7 +120,7 @@ void rmdf_params_default(rmdf_params *p);
  * Allocates all device state (observer state H*W*Kx*Ky*Kt/2 complex FP32, or
  * the ring of Kt 2-D spectra of the same size with RMDF_TEMPORAL_RING or
  * RMDF_TEMPORAL_DIRECT,
- * smoothed autocorrelation H*W*nvx*nvy FP32, row spectra, a (m'_t+1)-frame
+ * smoothed autocorrelation H*W*nvx*nvy FP32, row spectra, a (m'_t+2)-frame
  * delay ring, tables) and zeroes it.
  * Compiled window shapes: 8x8x4, 16x16x8, 9x9x5 (others: RMDF_E_UNSUPPORTED).
  * Errors: RMDF_E_INVAL (H, W < 1 or H > 65535; bad B, m', alpha, conf_threshold; nvx, nvy outside [1, 33],
@@ -149,7 +149,8 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt,
  * so a refused push changes nothing: not the frame count, the delay ring nor
  * the non-finite counter.  Frames smaller than the window are accepted (the
  * samples outside the frame count as zero).
- * Errors: RMDF_E_INVAL (NULL), RMDF_E_STATE (learned mode without weights),
+ * Errors: RMDF_E_INVAL (NULL), RMDF_E_STATE (learned mode without weights,
+ * or a stream owned by a batch: those advance with rmdf_batch_push),
  * RMDF_E_DEVICE (launch failure). */
 rmdf_status rmdf_push_frame(rmdf_ctx *ctx, const float *frame_dev);
 
@@ -165,7 +166,7 @@ rmdf_status rmdf_push_frame(rmdf_ctx *ctx, const float *frame_dev);
  * (H*W FP32, as rmdf_output); rmdf_output and rmdf_velocity then refer to the
  * last frame.  Every argument and state check precedes the first launch.
  * Errors: RMDF_E_INVAL (NULL ctx or frame, n < 1), RMDF_E_STATE (learned mode
- * without weights), RMDF_E_DEVICE. */
+ * without weights, or a stream owned by a batch), RMDF_E_DEVICE. */
 rmdf_status rmdf_push_frames(rmdf_ctx *ctx, int n, const float *const *frames_dev, float *const *out_dev);
 
 /* Copy the velocity field of the latest frame into caller buffers:
@@ -331,6 +332,38 @@ rmdf_status rmdf_hbm_probe(int kind, const void *src, void *dst, size_t bytes, i
 /* Bytes of device memory the context holds. */
 rmdf_status rmdf_device_bytes(const rmdf_ctx *ctx, size_t *bytes);
 
+/* ---- Checkpoint and restore ---------------------------------------------
+ * The filter is recursive in time (Sec. 1): all it carries from frame to
+ * frame is the observer state (or, in the temporal ring and direct forms,
+ * the ring of the last Kt 2-D spectra), the smoothed autocorrelation R'
+ * (Sec. 2, eq. 9-10 with the exponential smoother), the delay ring of raw
+ * frames (eq. 1 and 4 read the frame m'_t back), the frame count and the
+ * non-finite counter.  A saved state holds exactly these, plus the latest
+ * output, velocity and index (so the readouts after a restore equal those
+ * before the save), behind a 128-byte header naming the context's shape.
+ * The learned mode's features and network outputs are not part of it (they
+ * are recomputed by the next push); its weights are set separately.
+ *
+ * rmdf_state_bytes: size of a saved state of this context.
+ * rmdf_save_state: writes it to buf (host or device memory, at least
+ *   rmdf_state_bytes bytes, owned by the caller); ordered after the pushes
+ *   already queued on the context stream; returns when the copy is complete.
+ *   Errors: RMDF_E_INVAL (NULL, buffer too small), RMDF_E_DEVICE.
+ * rmdf_load_state: replaces the context's state by one saved from a context
+ *   created with the same frame size, window, candidate grid (values, not
+ *   only sizes), parameters (B, m', alpha, velocity mode, fixed velocity,
+ *   kernel variant, temporal form); the next push continues that stream bit
+ *   for bit as the saved context would have.  Returns when the copy is
+ *   complete.  Errors: RMDF_E_INVAL (NULL, short buffer, not a saved state,
+ *   or saved from a different configuration; the context is then unchanged),
+ *   RMDF_E_STATE (a stream owned by a batch), RMDF_E_DEVICE.
+ * Because the observer is deadbeat, a state whose spectrum part is damaged
+ * (any finite values) is flushed exactly after Kt pushes in exact arithmetic;
+ * the smoothed R then forgets it geometrically (factor alpha per frame). */
+rmdf_status rmdf_state_bytes(const rmdf_ctx *ctx, size_t *bytes);
+rmdf_status rmdf_save_state(rmdf_ctx *ctx, void *buf, size_t bytes);
+rmdf_status rmdf_load_state(rmdf_ctx *ctx, const void *buf, size_t bytes);
+
 /* Free everything; ctx may be NULL. */
 rmdf_status rmdf_destroy(rmdf_ctx *ctx);
 
@@ -350,7 +383,9 @@ typedef struct {
 
 /* Create n streams (p applies to all; NULL: defaults).  hip_stream: stream to
  * run on; NULL creates one (a captured graph cannot run on the null stream).
- * Errors as rmdf_create, reported for the first failing stream. */
+ * Errors as rmdf_create, reported for the first failing stream;
+ * RMDF_E_UNSUPPORTED for a velocity mode other than search or fixed, a
+ * temporal form other than the observer, or write_features. */
 rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc *streams, const rmdf_params *p,
                               void *hip_stream, rmdf_batch **out);
 /* Device address where the next frame of stream s (H*W FP32) must be written

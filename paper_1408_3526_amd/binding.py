@@ -62,6 +62,9 @@ _SIGS = {
     "rmdf_set_timing": (_I, [_VP, _I]),
     "rmdf_kernel_time": (_I, [_VP, _I, ctypes.POINTER(_D), ctypes.POINTER(_LL)]),
     "rmdf_device_bytes": (_I, [_VP, ctypes.POINTER(_SZ)]),
+    "rmdf_state_bytes": (_I, [_VP, ctypes.POINTER(_SZ)]),
+    "rmdf_save_state": (_I, [_VP, _VP, _SZ]),
+    "rmdf_load_state": (_I, [_VP, _VP, _SZ]),
     "rmdf_kernel_variant": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_coeff_lattice": (_I, [_VP, ctypes.POINTER(_I)]),
     "rmdf_tile_rows": (_I, [_VP, ctypes.POINTER(_I)]),
@@ -149,6 +152,23 @@ def _dev_ptr(t, dtype=None, numel=None, name="tensor"):
     if numel is not None and t.numel() != numel:
         raise ValueError("%s must have %d elements, has %d" % (name, numel, t.numel()))
     return t.data_ptr()
+
+
+def _buf_ptr(buf, writable):
+    """Address and size in bytes of a contiguous byte buffer: a CUDA tensor or
+    a numpy array in host memory."""
+    import torch
+    if isinstance(buf, torch.Tensor):
+        if not buf.is_cuda:
+            raise TypeError("state buffer tensors must be on the HIP device (use a numpy array for host memory)")
+        if not buf.is_contiguous():
+            raise ValueError("state buffer must be contiguous")
+        return buf.data_ptr(), buf.numel() * buf.element_size()
+    if isinstance(buf, np.ndarray):
+        if not buf.flags["C_CONTIGUOUS"] or (writable and not buf.flags["WRITEABLE"]):
+            raise ValueError("state buffer must be a contiguous%s numpy array" % (" writable" if writable else ""))
+        return buf.ctypes.data, buf.nbytes
+    raise TypeError("state buffer must be a CUDA tensor or a numpy array")
 
 
 # ---- C-named functions -------------------------------------------------------
@@ -362,6 +382,29 @@ class Filter:
         n = ctypes.c_size_t()
         _check(lib().rmdf_device_bytes(self.ctx, ctypes.byref(n)), self.ctx)
         return n.value
+
+    def state_bytes(self) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().rmdf_state_bytes(self.ctx, ctypes.byref(n)), self.ctx)
+        return n.value
+
+    def save_state(self, buf=None):
+        """rmdf_save_state into buf (a uint8 CUDA tensor or a writable uint8
+        numpy array of at least state_bytes() bytes; None: a new CUDA tensor),
+        which is returned."""
+        import torch
+        n = self.state_bytes()
+        if buf is None:
+            buf = torch.empty(n, dtype=torch.uint8, device="cuda")
+        ptr, size = _buf_ptr(buf, writable=True)
+        _check(lib().rmdf_save_state(self.ctx, ptr, size), self.ctx)
+        return buf
+
+    def load_state(self, buf):
+        """rmdf_load_state from a buffer written by save_state (CUDA tensor or
+        numpy array)."""
+        ptr, size = _buf_ptr(buf, writable=False)
+        _check(lib().rmdf_load_state(self.ctx, ptr, size), self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

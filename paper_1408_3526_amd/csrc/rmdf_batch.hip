@@ -387,6 +387,12 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
     delete b;
     return bfail(nullptr, st, m);
   };
+  if (p && p->velocity_mode != RMDF_VEL_SEARCH && p->velocity_mode != RMDF_VEL_FIXED)
+    return bail(RMDF_E_UNSUPPORTED, "batched streams support the search and fixed velocity modes");
+  if (p && p->temporal != RMDF_TEMPORAL_OBSERVER)
+    return bail(RMDF_E_UNSUPPORTED, "batched streams use the observer state (temporal mode 0)");
+  if (p && p->write_features)
+    return bail(RMDF_E_UNSUPPORTED, "batched streams do not write the learned model's features");
   std::vector<RowDesc> rd(n);
   int base = 0;
   for (int s = 0; s < n; ++s) {
@@ -394,10 +400,7 @@ rmdf_status rmdf_batch_create(int n, const rmdf_stream_desc* sd, const rmdf_para
     rmdf_status st = rmdf_create(sd[s].H, sd[s].W, sd[s].Kx, sd[s].Ky, sd[s].Kt, sd[s].vgrid_x, sd[s].nvx,
                                  sd[s].vgrid_y, sd[s].nvy, p, b->stream, &c);
     if (st != RMDF_OK) return bail(st, std::string("stream ") + std::to_string(s) + ": " + rmdf_last_error(nullptr));
-    if (p && p->velocity_mode != RMDF_VEL_SEARCH && p->velocity_mode != RMDF_VEL_FIXED)
-      return bail(RMDF_E_UNSUPPORTED, "batched streams support the search and fixed velocity modes");
-    if (p && p->temporal != RMDF_TEMPORAL_OBSERVER)
-      return bail(RMDF_E_UNSUPPORTED, "batched streams use the observer state (temporal mode 0)");
+    rmdf_internal_set_batch_owned(c);
     b->ctx.push_back(c);
     PixArgs a = rmdf_internal_pixargs(c);
     b->tile_rows.push_back(a.TY);

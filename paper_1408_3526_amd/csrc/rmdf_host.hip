@@ -67,6 +67,8 @@ struct rmdf_ctx {
   unsigned short *w1 = nullptr, *w2 = nullptr;   // BF16: W1 in the network kernel's operand order, W2 [64][128]
   float *b1 = nullptr, *b2 = nullptr, *w3 = nullptr, *b3 = nullptr;
   bool weights_set = false;
+  bool batch_owned = false;        // advanced by a batch's step, not by pushes
+  unsigned long long param_hash = 0;   // grid values and parameters (saved states)
   unsigned long long* nonfinite = nullptr;
   int* xy_scratch = nullptr;
   int xy_cap = 0;
@@ -306,6 +308,17 @@ void rmdf_internal_shape(const rmdf_ctx* c, int* mx, int* my, int* mz, int* vari
   *mx = c->MX; *my = c->MY; *mz = c->MZ; *variant = c->variant;
 }
 void rmdf_internal_advance(rmdf_ctx* c) { c->t += 1; }
+void rmdf_internal_set_batch_owned(rmdf_ctx* c) { c->batch_owned = true; }
+
+// FNV-1a over raw bytes (identifies the configuration a saved state belongs to).
+static unsigned long long fnv1a(unsigned long long h, const void* p, size_t n) {
+  const unsigned char* b = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; ++i) {
+    h ^= b[i];
+    h *= 0x100000001b3ull;
+  }
+  return h;
+}
 
 // Frame pairs run on the 16x16x8 one-wavefront-per-anchor kernel in its
 // observer form with the search or a fixed velocity.
@@ -415,6 +428,15 @@ rmdf_status rmdf_create(int H, int W, int Kx, int Ky, int Kt, const float* vgrid
                                                                         : rmdf::pixel_block_columns(Kx, Ky, Kt));
   c->write_features = p.write_features ? 1 : 0;
   c->temporal = p.temporal;
+  {
+    unsigned long long h = 0xcbf29ce484222325ull;
+    h = fnv1a(h, vgrid_x, sizeof(float) * nvx);
+    h = fnv1a(h, vgrid_y, sizeof(float) * nvy);
+    const int iv[8] = {Bx, By, dx, dy, dt, p.velocity_mode, c->write_features, c->variant};
+    const float fv[3] = {alpha, p.fixed_vx, p.fixed_vy};
+    h = fnv1a(h, iv, sizeof iv);
+    c->param_hash = fnv1a(h, fv, sizeof fv);
+  }
   // one slot beyond the delay: a frame pair stores its second frame before
   // the pair's first frame has read its delayed sample
   c->nring = dt + 2;
@@ -501,6 +523,7 @@ rmdf_status rmdf_push_frame(rmdf_ctx* c, const float* frame) {
   if (!frame) return fail(c, RMDF_E_INVAL, "frame is NULL");
   // every check precedes the first launch: a refused push leaves the delay
   // ring, the non-finite counter and the frame count as they were
+  if (c->batch_owned) return fail(c, RMDF_E_STATE, "stream owned by a batch: it advances with rmdf_batch_push");
   if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
   const size_t HW = (size_t)c->H * c->W;
   float* slot = c->ring + HW * (size_t)(c->t % c->nring);
@@ -579,6 +602,7 @@ rmdf_status rmdf_push_frames(rmdf_ctx* c, int n, const float* const* frames, flo
   if (n < 1 || !frames) return fail(c, RMDF_E_INVAL, "n must be >= 1 and frames non-NULL");
   for (int i = 0; i < n; ++i)
     if (!frames[i]) return fail(c, RMDF_E_INVAL, "frame is NULL");
+  if (c->batch_owned) return fail(c, RMDF_E_STATE, "stream owned by a batch: it advances with rmdf_batch_push");
   if (c->vmode == RMDF_VEL_LEARNED && !c->weights_set) return fail(c, RMDF_E_STATE, "learned mode: weights not set");
   const size_t bytes = (size_t)c->H * c->W * sizeof(float);
   for (int i = 0; i < n;) {
@@ -853,6 +877,125 @@ rmdf_status rmdf_learned_network(rmdf_ctx* c, const void* feat_dev, int n, float
   if (reinterpret_cast<uintptr_t>(feat_dev) & 15) return fail(c, RMDF_E_INVAL, "features not 16-byte aligned");
   const hipError_t e = run_network(c, static_cast<const unsigned short*>(feat_dev), n, vc_dev, nullptr);
   if (e != hipSuccess) return hip_fail(c, e, "network launch");
+  return RMDF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Saved states: a 128-byte header, then the sections below, each starting on a
+// 256-byte boundary.
+namespace {
+struct StateHeader {
+  char magic[8];                   // "RMDFST1"
+  unsigned int version, header_bytes;
+  int H, W, MX, MY, MZ, nvx, nvy, variant, temporal, nring, dt, reserved;
+  long long t;                     // frames pushed
+  unsigned long long nonfinite;    // non-finite samples replaced so far
+  unsigned long long param_hash;
+  unsigned char pad[40];
+};
+static_assert(sizeof(StateHeader) == 128, "state header layout");
+constexpr char kStateMagic[8] = {'R', 'M', 'D', 'F', 'S', 'T', '1', 0};
+constexpr size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+struct Section {
+  void* dev;
+  size_t bytes;
+};
+}  // namespace
+
+// The recursive state: observer (or 2-D spectrum ring), smoothed R, delay
+// ring; then the latest readouts.
+static std::vector<Section> state_sections(const rmdf_ctx* c) {
+  const size_t HW = (size_t)c->H * c->W;
+  return {{c->st, HW * c->NCOL * c->MZ * sizeof(float2)},
+          {c->rsm, HW * c->nv * sizeof(float)},
+          {c->ring, HW * c->nring * sizeof(float)},
+          {c->out, HW * sizeof(float)},
+          {c->vxy, HW * sizeof(float2)},
+          {c->vidx, HW * sizeof(int)}};
+}
+
+static size_t state_size(const rmdf_ctx* c) {
+  size_t n = sizeof(StateHeader);
+  for (const Section& sec : state_sections(c)) n = align256(n) + sec.bytes;
+  return n;
+}
+
+static StateHeader state_header(const rmdf_ctx* c) {
+  StateHeader h;
+  std::memset(&h, 0, sizeof h);
+  std::memcpy(h.magic, kStateMagic, sizeof h.magic);
+  h.version = 1;
+  h.header_bytes = sizeof(StateHeader);
+  h.H = c->H; h.W = c->W; h.MX = c->MX; h.MY = c->MY; h.MZ = c->MZ;
+  h.nvx = c->nvx; h.nvy = c->nvy; h.variant = c->variant; h.temporal = c->temporal;
+  h.nring = c->nring; h.dt = c->dt;
+  h.param_hash = c->param_hash;
+  h.t = c->t;
+  return h;
+}
+
+rmdf_status rmdf_state_bytes(const rmdf_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return RMDF_E_INVAL;
+  *bytes = state_size(c);
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_save_state(rmdf_ctx* c, void* buf, size_t bytes) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (!buf) return fail(c, RMDF_E_INVAL, "buffer is NULL");
+  if (bytes < state_size(c)) return fail(c, RMDF_E_INVAL, "buffer smaller than rmdf_state_bytes");
+  StateHeader h = state_header(c);
+  hipError_t e = hipMemcpyAsync(&h.nonfinite, c->nonfinite, sizeof h.nonfinite, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "counter read");
+  char* dst = static_cast<char*>(buf);
+  if ((e = hipMemcpyAsync(dst, &h, sizeof h, hipMemcpyDefault, c->stream)) != hipSuccess) return hip_fail(c, e, "save");
+  size_t off = sizeof h;
+  for (const Section& sec : state_sections(c)) {
+    off = align256(off);
+    if ((e = hipMemcpyAsync(dst + off, sec.dev, sec.bytes, hipMemcpyDefault, c->stream)) != hipSuccess)
+      return hip_fail(c, e, "save");
+    off += sec.bytes;
+  }
+  // the header lives on this stack frame: wait for the copies
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "save");
+  return RMDF_OK;
+}
+
+rmdf_status rmdf_load_state(rmdf_ctx* c, const void* buf, size_t bytes) {
+  if (!c) return fail(nullptr, RMDF_E_INVAL, "ctx is NULL");
+  if (!buf) return fail(c, RMDF_E_INVAL, "buffer is NULL");
+  if (c->batch_owned) return fail(c, RMDF_E_STATE, "stream owned by a batch: its frame count lives in the batch");
+  if (bytes < sizeof(StateHeader)) return fail(c, RMDF_E_INVAL, "buffer too small for a saved state");
+  StateHeader h;
+  hipError_t e = hipMemcpyAsync(&h, buf, sizeof h, hipMemcpyDefault, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "header read");
+  const StateHeader mine = state_header(c);
+  if (std::memcmp(h.magic, kStateMagic, sizeof h.magic) != 0 || h.version != 1 || h.header_bytes != sizeof h)
+    return fail(c, RMDF_E_INVAL, "not a saved rmdf state");
+  if (h.H != mine.H || h.W != mine.W || h.MX != mine.MX || h.MY != mine.MY || h.MZ != mine.MZ ||
+      h.nvx != mine.nvx || h.nvy != mine.nvy || h.variant != mine.variant || h.temporal != mine.temporal ||
+      h.nring != mine.nring || h.dt != mine.dt)
+    return fail(c, RMDF_E_INVAL, "saved state belongs to a context of another shape");
+  if (h.param_hash != mine.param_hash)
+    return fail(c, RMDF_E_INVAL, "saved state belongs to a context with another grid or parameters");
+  if (h.t < 0) return fail(c, RMDF_E_INVAL, "saved state has a negative frame count");
+  if (bytes < state_size(c)) return fail(c, RMDF_E_INVAL, "buffer shorter than the saved state");
+  const char* src = static_cast<const char*>(buf);
+  size_t off = sizeof h;
+  for (const Section& sec : state_sections(c)) {
+    off = align256(off);
+    if ((e = hipMemcpyAsync(sec.dev, src + off, sec.bytes, hipMemcpyDefault, c->stream)) != hipSuccess)
+      return hip_fail(c, e, "load");
+    off += sec.bytes;
+  }
+  if ((e = hipMemcpyAsync(c->nonfinite, &h.nonfinite, sizeof h.nonfinite, hipMemcpyHostToDevice, c->stream)) !=
+      hipSuccess)
+    return hip_fail(c, e, "load");
+  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "load");
+  c->t = h.t;
   return RMDF_OK;
 }
 

@@ -15,6 +15,9 @@ unsigned long long* rmdf_internal_nonfinite(const rmdf_ctx* c);
 void rmdf_internal_shape(const rmdf_ctx* c, int* mx, int* my, int* mz, int* variant);
 // Count one frame pushed by someone else (the batched step).
 void rmdf_internal_advance(rmdf_ctx* c);
+// Mark a context as one stream of a batch (single pushes and state loads are
+// then refused: the batch's step advances it).
+void rmdf_internal_set_batch_owned(rmdf_ctx* c);
 void rmdf_internal_set_create_error(const std::string& m);
 
 namespace rmdf {

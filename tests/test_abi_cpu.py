@@ -91,6 +91,9 @@ def test_null_context_calls(L):
     assert L.rmdf_velocity(None, None, None) == -1
     assert L.rmdf_spectrum_noalloc(None, 0, None, None, None) == -1
     assert L.rmdf_push_frames(None, 2, None, None) == -1
+    assert L.rmdf_state_bytes(None, None) == -1
+    assert L.rmdf_save_state(None, None, 0) == -1
+    assert L.rmdf_load_state(None, None, 0) == -1
     assert L.rmdf_destroy(None) == 0
 
 
