@@ -38,7 +38,7 @@ LEARNED_EVAL_SEEDS = (2000, 2001, 2002)
 TIMING_EVERY = 8
 
 KERNEL_SOURCES = ["paper_1408_3526_amd/csrc/rmdf_pixel16.h", "paper_1408_3526_amd/csrc/rmdf_pixel16.hip",
-                  "paper_1408_3526_amd/csrc/rmdf_kernels.h"]
+                  "paper_1408_3526_amd/csrc/rmdf_kernels.h", "paper_1408_3526_amd/csrc/rmdf_wave.h"]
 
 WORKLOADS = {
     "640x512": dict(H=512, W=640, M=(16, 16, 8), grid=(-4.0, 4.0, 0.5), frames=200, seed=1, targets=20),

@@ -8,6 +8,7 @@
 
 #include "rmdf_kernels.h"
 #include "rmdf_refine.h"
+#include "rmdf_wave.h"
 
 namespace rmdf {
 
@@ -63,10 +64,12 @@ static __device__ void row_chunk(const float* __restrict__ f, float2* __restrict
   }
   for (int i = threadIdx.x; i < MX; i += blockDim.x) s_tw[i] = twx[i];
   if (nonfinite) {
-    const unsigned long long m = __ballot(bad != 0);
-    int tot = bad;
-    for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
-    if (m && (threadIdx.x & 63) == 0) atomicAdd(nonfinite, (unsigned long long)tot);
+    // the wavefront's count, reduced only where it has non-finite samples
+    if (__ballot(bad != 0)) {
+      int tot = bad;
+      for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off, 64);
+      if ((threadIdx.x & 63) == 0) atomicAdd(nonfinite, (unsigned long long)tot);
+    }
   }
   __syncthreads();
   const float inv = rsqrtf((float)MX);
@@ -158,10 +161,6 @@ struct Shape {
                                  (sizeof(float) + sizeof(int)) * 256;
 };
 
-// (value, index) argmax with the first (lowest-index) maximum winning.
-static __device__ __forceinline__ void amax_merge(float& v, int& i, float v2, int i2) {
-  if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
-}
 
 // Eq. (8) at bin (kx, ky, kz) for a continuous velocity (the spatial Dirichlet
 // factors select kx' = kx, ky' = ky at the bins), times sqrt(Mz) since the
@@ -411,13 +410,9 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
         amax_merge(bv, bi, sm, w);
       }
     }
-    // reduce (value, index) over the pixel's NCOLP threads
-#pragma unroll
-    for (int off = (NCOLP < 64 ? NCOLP : 64) / 2; off > 0; off >>= 1) {
-      const float v2 = __shfl_xor(bv, off, 64);
-      const int i2 = __shfl_xor(bi, off, 64);
-      amax_merge(bv, bi, v2, i2);
-    }
+    // reduce (value, index) over the pixel's NCOLP threads (within the
+    // wavefront by DPP and lane reads, across wavefronts through LDS)
+    group_amax<(NCOLP < 64 ? NCOLP : 64)>(bv, bi);
     if (NCOLP > 64) {
       s_rv[tid] = bv;
       s_ri[tid] = bi;
@@ -461,8 +456,7 @@ static __device__ __forceinline__ void pixel_tile(const PixArgs& a, const float*
         }
       }
     }
-#pragma unroll
-    for (int off = (NCOLP < 64 ? NCOLP : 64) / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    acc = group_sum<(NCOLP < 64 ? NCOLP : 64)>(acc);
     if (NCOLP > 64) {
       s_rv[tid] = acc;
       lds_barrier();

@@ -25,6 +25,7 @@
 
 #include "rmdf_kernels.h"
 #include "rmdf_refine.h"
+#include "rmdf_wave.h"
 
 namespace rmdf {
 namespace p16 {
@@ -78,48 +79,11 @@ __device__ __forceinline__ void st4(lds_v2* p, float a, float b, float c, float 
 }
 
 template <int CTRL>
-static __device__ __forceinline__ float dppf(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-static __device__ __forceinline__ int dppi(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
-}
-// row_ror:n -> dst[i] = src[(i - n) mod 16] within each row of 16 lanes;
-// row_mirror -> dst[i] = src[15 - i]; quad_perm [1,0,3,2] and [2,3,0,1] ->
-// dst[i] = src[i ^ 1] and src[i ^ 2]
-constexpr int ROR1 = 0x121, ROR4 = 0x124, ROR8 = 0x128, ROR15 = 0x12F, MIRROR = 0x140, QXOR1 = 0xB1,
-              QXOR2 = 0x4E;
-
-template <int CTRL>
 static __device__ __forceinline__ float2 dpp2(float2 v) { return f2(dppf<CTRL>(v.x), dppf<CTRL>(v.y)); }
 
 // value held by lane (r, -ky mod 16) of the same row: the row mirrored
 // (lane j gets 15 - j), then rotated by one
 static __device__ __forceinline__ float2 row_neg(float2 v) { return dpp2<ROR1>(dpp2<MIRROR>(v)); }
-
-static __device__ __forceinline__ float lane_read(float v, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-
-// Wavefront reductions, the result uniform: within each row of 16 lanes by
-// DPP (partners lane ^ 1, lane ^ 2, then rotations by 4 and 8, after which
-// every lane holds its row's result), then the four rows' results read from
-// lanes 0, 16, 32 and 48.  Every lane of the wavefront must be active.
-static __device__ __forceinline__ float wave_sum(float v) {
-  v += dppf<QXOR1>(v);
-  v += dppf<QXOR2>(v);
-  v += dppf<ROR4>(v);
-  v += dppf<ROR8>(v);
-  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
-}
-static __device__ __forceinline__ float wave_max(float v) {
-  v = fmaxf(v, dppf<QXOR1>(v));
-  v = fmaxf(v, dppf<QXOR2>(v));
-  v = fmaxf(v, dppf<ROR4>(v));
-  v = fmaxf(v, dppf<ROR8>(v));
-  return fmaxf(fmaxf(lane_read(v, 0), lane_read(v, 16)), fmaxf(lane_read(v, 32), lane_read(v, 48)));
-}
 
 static __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -150,28 +114,6 @@ static __device__ __forceinline__ float2 rot8(float2 a, int k) {
     case 6: return f2(a.y, -a.x);
     default: return f2((a.x + a.y) * c, (a.y - a.x) * c);
   }
-}
-
-static __device__ __forceinline__ void amax_merge(float& v, int& i, float v2, int i2) {
-  const bool take = (v2 > v) | ((v2 == v) & (i2 < i));
-  v = take ? v2 : v;
-  i = take ? i2 : i;
-}
-
-// First maximum over the wavefront (largest value, lowest index among equal
-// values), uniform: the merge is a maximum over a total order, so the
-// reduction's shape (as in wave_sum) does not change the result.
-static __device__ __forceinline__ void wave_amax(float& v, int& i) {
-  amax_merge(v, i, dppf<QXOR1>(v), dppi<QXOR1>(i));
-  amax_merge(v, i, dppf<QXOR2>(v), dppi<QXOR2>(i));
-  amax_merge(v, i, dppf<ROR4>(v), dppi<ROR4>(i));
-  amax_merge(v, i, dppf<ROR8>(v), dppi<ROR8>(i));
-  float bv = lane_read(v, 0);
-  int bi = __builtin_amdgcn_readlane(i, 0);
-#pragma unroll
-  for (int r = 16; r < 64; r += 16) amax_merge(bv, bi, lane_read(v, r), __builtin_amdgcn_readlane(i, r));
-  v = bv;
-  i = bi;
 }
 
 // sum_kz P_kz w_8^kz / 512 (stage A of the autocorrelation at l_z = 1: the
@@ -678,7 +620,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
         float mx = 0.f;
 #pragma unroll
         for (int k = 0; k < MZ; ++k) mx = fmaxf(mx, fmaxf(PA[k], fmaxf(PB[k], r == 0 ? P8[k] : 0.f)));
-        mx = wave_max(mx);
+        mx = group_max<64>(mx);
         const float eps = fmaxf(1e-6f * mx, 1e-30f);
         float sum = 0.f;
 #pragma unroll
@@ -688,7 +630,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
           P8[k] = (r == 0) ? __logf(P8[k] + eps) : 0.f;
           sum += (r == 0 ? 1.f : 2.f) * PA[k] + 2.f * PB[k] + P8[k];
         }
-        sum = wave_sum(sum);
+        sum = group_sum<64>(sum);
         const float mean = sum * (1.0f / (MX * MY * MZ));
         unsigned short* fp = a.feat + pix * (NXH * MY * MZ);
         auto put8 = [&](int kx, const float* L) {
@@ -786,7 +728,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
           __builtin_amdgcn_sched_barrier(0);   // keep one iteration's LDS reads in flight at a time
         }
       }
-      wave_amax(bv, bi);
+      group_amax<64>(bv, bi);
       const int istar = (bi < nv) ? bi : 0;
       if (MODE == 2 && lane == 0) a.fidx[pix] = istar;
 
@@ -849,7 +791,7 @@ static __device__ __forceinline__ void pixel16_tile(const PixArgs& a, const floa
           for (int k = 0; k < MZ; ++k) acc += h[k].x * XB[k].x - h[k].y * XB[k].y;
         }
       }
-      acc = wave_sum(acc);
+      acc = group_sum<64>(acc);
       if (lane == 0 && !LAST) {
         if (!isfinite(idel)) idel = 0.f;
         a.out_first[pix] = idel - acc;   // the pair's first frame: its output only
@@ -898,7 +840,7 @@ static __device__ void finish16(const PixArgs& a, const float* ring_delayed, con
       acc += pef_plane16(xl, p, kyc, vx, vy, a.dx, a.dy, a.dt);
     }
   }
-  acc = wave_sum(acc);
+  acc = group_sum<64>(acc);
   if (lane == 0) {
     const int xs = x - a.dx, ys = y - a.dy;
     float idel = (ring_delayed != nullptr && xs >= 0 && ys >= 0) ? ring_delayed[(size_t)ys * a.W + xs] : 0.f;
