@@ -52,3 +52,43 @@ def test_smoothing_makes_the_gpu_path_robust_to_noise(noise):
         f.close()
         rates.append(_hit_rate(np.stack(vs)))
     assert rates[1] >= 0.95 and rates[1] >= rates[0] + 0.15, rates
+
+
+@pytest.mark.gpu
+def test_processing_load_does_not_depend_on_the_data():
+    """Sec. 1: the processing load is uniform and independent of the data.
+    The per-pixel kernel's time on all-zero frames, on white noise and on a
+    textured moving scene agrees within 20% (medians of interleaved timed
+    blocks; the kernels have no data-dependent control flow in the plain
+    search)."""
+    torch = pytest.importorskip("torch")
+    from paper_1408_3526_amd import binding
+    H, W = 256, 320
+    g = scenes.grid(-4, 4, 0.5)
+    rng = np.random.default_rng(0)
+    inputs = {
+        "zero": np.zeros((8, H, W), np.float32),
+        "noise": rng.normal(size=(8, H, W)).astype(np.float32),
+        "scene": scenes.flow_scene(9, H=H, W=W, T=8, n_targets=5).frames,
+    }
+    times = {k: [] for k in inputs}
+    filters = {k: binding.Filter(H, W, 16, 16, 8, g, g) for k in inputs}
+    devs = {k: torch.from_numpy(v).cuda() for k, v in inputs.items()}
+    for k in inputs:
+        for t in range(16):
+            filters[k].push_frame(devs[k][t % 8])
+    torch.cuda.synchronize()
+    for _ in range(5):
+        for k in inputs:
+            f = filters[k]
+            f.set_timing(kernels=[0])
+            f.kernel_time(0)
+            for t in range(20):
+                f.push_frame(devs[k][t % 8])
+            ms, n = f.kernel_time(0)
+            f.set_timing(False)
+            times[k].append(ms / n)
+    for f in filters.values():
+        f.close()
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    assert max(med.values()) <= 1.2 * min(med.values()), med
