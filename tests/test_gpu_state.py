@@ -206,3 +206,28 @@ def _observer_bytes(case):
     Mx, My, Mz = CASES[case]["M"]
     planes = {8: 4, 9: 5, 16: 8}[Mx]
     return H * W * planes * My * Mz * 8
+
+
+def test_restore_then_frame_pairs_equals_single_pushes():
+    """A state saved after an odd number of frames, restored, and continued by
+    frame pairs gives what the saved context gives by single pushes (the
+    ring slot arithmetic and the pair kernel both resume from the saved frame
+    count)."""
+    dev = _frames()
+    a = _filter("16x16x8")
+    for t in range(5):
+        a.push_frame(dev[t])
+    blob = a.save_state()
+    ref = []
+    for t in range(5, T):
+        a.push_frame(dev[t])
+        ref.append(a.output().cpu().numpy())
+    a.close()
+    b = _filter("16x16x8")
+    b.load_state(blob)
+    outs = [torch.empty(H, W, device="cuda") for _ in range(5, T)]
+    b.push_frames([dev[t] for t in range(5, T)], outs)
+    for k, o in enumerate(outs):
+        assert np.array_equal(o.cpu().numpy(), ref[k]), k
+    assert b.frames_pushed() == T
+    b.close()
