@@ -91,4 +91,5 @@ def test_processing_load_does_not_depend_on_the_data():
     for f in filters.values():
         f.close()
     med = {k: float(np.median(v)) for k, v in times.items()}
+    print("median pixel-kernel ms per frame:", med)
     assert max(med.values()) <= 1.2 * min(med.values()), med
